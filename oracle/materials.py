@@ -1,0 +1,192 @@
+"""Energy density, stress and tangent in closed form (oracle).
+
+These are the paper's "analytical implementation" counterparts of the
+automatic-differentiation path (section 3.1: stress is the derivative of the
+energy density; section 3.2: the incremental stress is the tangent applied to a
+strain increment).  Every function accepts real or complex arrays so that the
+CPU tests can pin them with complex-step derivatives.
+
+Arguments: strain-like tensors ``E`` of shape (*grid, d, d); Lame parameters
+``lam``, ``mu`` broadcastable to the grid.  d = 2 means plane strain: the
+out-of-plane strain is zero (F33 = 1 for finite strain).
+
+Readings of the paper used here:
+* linear elastic energy  psi = lam/2 tr(eps)^2 + mu eps:eps.  The paper prints
+  it without the 1/2 and with a trace on the scalar; its Table 1 values
+  (C_xxxx about 4.04 for a lam=2, mu=1 matrix, i.e. lam + 2 mu) fix the 1/2.
+* St. Venant-Kirchhoff (section 4.1.1, hyperelastic energy): Green-Lagrange
+  strain E = (F^T F - I)/2, psi = lam/2 tr(E)^2 + mu E:E.
+* compressible Neo-Hookean (not written out in the paper):
+  psi = mu/2 (I1 - 3) - mu ln J + lam/2 (ln J)^2, I1 = tr(F^T F).
+"""
+
+import numpy as np
+
+
+def _eye(d):
+    return np.eye(d)
+
+
+def _tr(A):
+    return np.einsum("...ii->...", A)
+
+
+def _lm(lam, mu):
+    lam = np.asarray(lam)
+    mu = np.asarray(mu)
+    return lam[..., None, None], mu[..., None, None]
+
+
+# ----------------------------------------------------------------------------
+# small strain, linear elastic
+# ----------------------------------------------------------------------------
+class LinearElastic:
+    kinematics = "small"
+
+    @staticmethod
+    def psi(eps, lam, mu):
+        lam = np.asarray(lam)
+        mu = np.asarray(mu)
+        tr = _tr(eps)
+        return 0.5 * lam * tr * tr + mu * np.einsum("...ij,...ij->...", eps, eps)
+
+    @staticmethod
+    def stress(eps, lam, mu):
+        d = eps.shape[-1]
+        L, M = _lm(lam, mu)
+        return L * _tr(eps)[..., None, None] * _eye(d) + 2.0 * M * eps
+
+    @staticmethod
+    def tangent_apply(eps, deps, lam, mu):
+        d = deps.shape[-1]
+        L, M = _lm(lam, mu)
+        return L * _tr(deps)[..., None, None] * _eye(d) + 2.0 * M * deps
+
+    @staticmethod
+    def tangent_tensor(eps, lam, mu):
+        d = eps.shape[-1]
+        I = _eye(d)
+        lam = np.asarray(lam)[..., None, None, None, None]
+        mu = np.asarray(mu)[..., None, None, None, None]
+        base = (
+            lam * np.einsum("ij,kl->ijkl", I, I)
+            + mu * (np.einsum("ik,jl->ijkl", I, I) + np.einsum("il,jk->ijkl", I, I))
+        )
+        return np.broadcast_to(base, eps.shape[:-2] + (d, d, d, d)).copy()
+
+
+# ----------------------------------------------------------------------------
+# finite strain, compressible Neo-Hookean
+# ----------------------------------------------------------------------------
+class NeoHookean:
+    kinematics = "finite"
+
+    @staticmethod
+    def _invariants(F):
+        d = F.shape[-1]
+        J = np.linalg.det(F)
+        I1 = np.einsum("...ij,...ij->...", F, F) + (3 - d)
+        return J, I1
+
+    @staticmethod
+    def psi(F, lam, mu):
+        lam = np.asarray(lam)
+        mu = np.asarray(mu)
+        J, I1 = NeoHookean._invariants(F)
+        lnJ = np.log(J)
+        return 0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ
+
+    @staticmethod
+    def stress(F, lam, mu):
+        L, M = _lm(lam, mu)
+        J = np.linalg.det(F)
+        FinvT = np.swapaxes(np.linalg.inv(F), -1, -2)
+        lnJ = np.log(J)[..., None, None]
+        return M * F + (L * lnJ - M) * FinvT
+
+    @staticmethod
+    def tangent_apply(F, dF, lam, mu):
+        L, M = _lm(lam, mu)
+        Finv = np.linalg.inv(F)
+        FinvT = np.swapaxes(Finv, -1, -2)
+        lnJ = np.log(np.linalg.det(F))[..., None, None]
+        tr = np.einsum("...ij,...ji->...", Finv, dF)[..., None, None]  # tr(F^-1 dF)
+        dFT = np.swapaxes(dF, -1, -2)
+        return M * dF + L * tr * FinvT - (L * lnJ - M) * (FinvT @ dFT @ FinvT)
+
+    @staticmethod
+    def tangent_tensor(F, lam, mu):
+        d = F.shape[-1]
+        I = _eye(d)
+        Finv = np.linalg.inv(F)
+        lnJ = np.log(np.linalg.det(F))[..., None, None, None, None]
+        lam = np.asarray(lam)[..., None, None, None, None]
+        mu = np.asarray(mu)[..., None, None, None, None]
+        t1 = np.einsum("ik,jl->ijkl", I, I)
+        t2 = np.einsum("...ji,...lk->...ijkl", Finv, Finv)
+        t3 = np.einsum("...jk,...li->...ijkl", Finv, Finv)
+        return mu * t1 + lam * t2 - (lam * lnJ - mu) * t3
+
+
+# ----------------------------------------------------------------------------
+# finite strain, St. Venant-Kirchhoff
+# ----------------------------------------------------------------------------
+class StVenantKirchhoff:
+    kinematics = "finite"
+
+    @staticmethod
+    def _green(F):
+        d = F.shape[-1]
+        return 0.5 * (np.swapaxes(F, -1, -2) @ F - _eye(d))
+
+    @staticmethod
+    def psi(F, lam, mu):
+        lam = np.asarray(lam)
+        mu = np.asarray(mu)
+        E = StVenantKirchhoff._green(F)
+        tr = _tr(E)
+        return 0.5 * lam * tr * tr + mu * np.einsum("...ij,...ij->...", E, E)
+
+    @staticmethod
+    def _S(E, L, M):
+        d = E.shape[-1]
+        return L * _tr(E)[..., None, None] * _eye(d) + 2.0 * M * E
+
+    @staticmethod
+    def stress(F, lam, mu):
+        L, M = _lm(lam, mu)
+        return F @ StVenantKirchhoff._S(StVenantKirchhoff._green(F), L, M)
+
+    @staticmethod
+    def tangent_apply(F, dF, lam, mu):
+        L, M = _lm(lam, mu)
+        S = StVenantKirchhoff._S(StVenantKirchhoff._green(F), L, M)
+        FT = np.swapaxes(F, -1, -2)
+        dE = 0.5 * (np.swapaxes(dF, -1, -2) @ F + FT @ dF)
+        return dF @ S + F @ StVenantKirchhoff._S(dE, L, M)
+
+    @staticmethod
+    def tangent_tensor(F, lam, mu):
+        d = F.shape[-1]
+        out = np.zeros(F.shape[:-2] + (d, d, d, d), dtype=np.result_type(F, 1.0))
+        for k in range(d):
+            for l in range(d):
+                dF = np.zeros(F.shape, dtype=out.dtype)
+                dF[..., k, l] = 1.0
+                out[..., :, :, k, l] = StVenantKirchhoff.tangent_apply(F, dF, lam, mu)
+        return out
+
+
+MATERIALS = {
+    "linear_elastic": LinearElastic,
+    "neo_hookean": NeoHookean,
+    "stvk": StVenantKirchhoff,
+}
+
+
+def lame_from_young(E, nu):
+    """Lame parameters from Young's modulus and Poisson ratio (3D / plane strain)."""
+    E = np.asarray(E, dtype=np.float64)
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu

@@ -1,0 +1,450 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each pin compares the oracle with something other than itself: analytic
+gradient fields, complex-step and finite-difference derivatives, the
+homogeneous-medium and laminate closed forms, the Voigt-Reuss bounds, a dense
+displacement-formulation solve built from explicit DFT matrices, and the
+paper's Table 1.  ``test_pins_detect_planted_mistakes`` plants plausible
+mistakes in the oracle (on the CPU) and checks that a pin fails.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce, closed_forms, materials, newton_cg, spectral
+from paper_2408_03804_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+def grid_coords(shape, lengths):
+    """Voxel-centre coordinates x_a (a = x, y, z) broadcast over the grid."""
+    d = len(shape)
+    out = []
+    for a in range(d):
+        axis = d - 1 - a
+        h = lengths[a] / shape[axis]
+        c = (np.arange(shape[axis]) + 0.5) * h
+        bs = [1] * d
+        bs[axis] = shape[axis]
+        out.append(np.broadcast_to(c.reshape(bs), shape))
+    return out
+
+
+def analytic_gradient(shape, lengths, seed, nterms=3):
+    """grad u of a random trigonometric periodic displacement, evaluated analytically."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    x = grid_coords(shape, lengths)
+    H = np.zeros(tuple(shape) + (d, d))
+    for _ in range(nterms):
+        m = []
+        for a in range(d):
+            n = shape[d - 1 - a]
+            kmax = (n - 1) // 2
+            m.append(int(rng.integers(-kmax, kmax + 1)) if kmax > 0 else 0)
+        amp = rng.standard_normal(d)
+        phi = rng.uniform(0, 2 * np.pi)
+        arg = sum(2 * np.pi * m[a] * x[a] / lengths[a] for a in range(d)) + phi
+        for i in range(d):
+            for j in range(d):
+                H[..., i, j] += -amp[i] * (2 * np.pi * m[j] / lengths[j]) * np.sin(arg)
+    return H
+
+
+def kernel_field(shape, lengths, seed, symmetric):
+    """cos(k.x) v (x) w with w orthogonal to k: annihilated by the projection."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    x = grid_coords(shape, lengths)
+    m = np.array([1, 2, 1][:d], dtype=float)
+    k = np.array([2 * np.pi * m[a] / lengths[a] for a in range(d)])
+    w = rng.standard_normal(d)
+    w -= k * (w @ k) / (k @ k)
+    v = w if symmetric else rng.standard_normal(d)
+    arg = sum(k[a] * x[a] for a in range(d))
+    return np.cos(arg)[..., None, None] * np.outer(v, w)
+
+
+def sym(A):
+    return 0.5 * (A + np.swapaxes(A, -1, -2))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+GRIDS = [((7, 9), (1.0, 1.3)), ((6, 8), (1.0, 1.0)), ((5, 6, 7), (1.0, 0.8, 1.2)), ((4, 6, 8), (1.0, 1.0, 1.0))]
+
+
+def projection_gradient_error(shape, lengths, kin, seed=0):
+    H = analytic_gradient(shape, lengths, seed)
+    if kin == "small":
+        H = sym(H)
+    return rel(spectral.apply_G(H, kin, lengths), H)
+
+
+def projection_kernel_error(shape, lengths, kin, seed=0):
+    A = kernel_field(shape, lengths, seed, symmetric=(kin == "small"))
+    return float(np.linalg.norm(spectral.apply_G(A, kin, lengths)) / np.linalg.norm(A))
+
+
+def stress_complex_step_error(mat, F, lam, mu):
+    h = 1e-30
+    d = F.shape[-1]
+    S = mat.stress(F, lam, mu)
+    cs = np.zeros_like(S)
+    for i in range(d):
+        for j in range(d):
+            Fc = F.astype(complex)
+            Fc[..., i, j] += 1j * h
+            cs[..., i, j] = mat.psi(Fc, lam, mu).imag / h
+    return rel(cs, S)
+
+
+def tangent_complex_step_error(mat, F, dF, lam, mu):
+    h = 1e-30
+    cs = mat.stress(F + 1j * h * dF, lam, mu).imag / h
+    return rel(cs, mat.tangent_apply(F, dF, lam, mu))
+
+
+def material_point(kin, d, seed, n=5):
+    rng = np.random.default_rng(seed)
+    if kin == "small":
+        F = sym(0.02 * rng.standard_normal((n, d, d)))
+    else:
+        F = np.eye(d) + 0.15 * rng.standard_normal((n, d, d))
+    lam = rng.uniform(0.5, 3.0, n)
+    mu = rng.uniform(0.5, 3.0, n)
+    return F, lam, mu
+
+
+# ----------------------------------------------------------------------------
+# projection
+# ----------------------------------------------------------------------------
+def test_wavenumbers_nyquist_rule():
+    assert np.allclose(spectral.axis_wavenumbers(4, 1.0), 2 * np.pi * np.array([0, 1, 0, -1]))
+    assert np.allclose(spectral.axis_wavenumbers(5, 2.0), np.pi * np.array([0, 1, 2, -2, -1]))
+
+
+@pytest.mark.parametrize("shape,lengths", GRIDS)
+@pytest.mark.parametrize("kin", ["small", "finite"])
+def test_projection_keeps_analytic_gradients(shape, lengths, kin):
+    assert projection_gradient_error(shape, lengths, kin) < 1e-13
+
+
+@pytest.mark.parametrize("shape,lengths", GRIDS)
+@pytest.mark.parametrize("kin", ["small", "finite"])
+def test_projection_annihilates_incompatible_modes(shape, lengths, kin):
+    assert projection_kernel_error(shape, lengths, kin) < 1e-13
+
+
+@pytest.mark.parametrize("shape,lengths", GRIDS)
+@pytest.mark.parametrize("kin", ["small", "finite"])
+def test_projection_idempotent_selfadjoint_zero_mean(shape, lengths, kin):
+    rng = np.random.default_rng(1)
+    d = len(shape)
+    a = rng.standard_normal(tuple(shape) + (d, d))
+    b = rng.standard_normal(tuple(shape) + (d, d))
+    if kin == "small":
+        a, b = sym(a), sym(b)
+    Ga = spectral.apply_G(a, kin, lengths)
+    Gb = spectral.apply_G(b, kin, lengths)
+    assert rel(spectral.apply_G(Ga, kin, lengths), Ga) < 1e-13
+    assert abs(spectral.inner(Ga, b) - spectral.inner(a, Gb)) < 1e-12 * np.linalg.norm(a) * np.linalg.norm(b)
+    assert np.abs(Ga.reshape(-1, d, d).mean(axis=0)).max() < 1e-14
+    U = np.broadcast_to(rng.standard_normal((d, d)), a.shape)
+    assert np.abs(spectral.apply_G(U, kin, lengths)).max() < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# constitutive laws
+# ----------------------------------------------------------------------------
+MATS = [("linear_elastic", "small"), ("neo_hookean", "finite"), ("stvk", "finite")]
+
+
+@pytest.mark.parametrize("name,kin", MATS)
+@pytest.mark.parametrize("d", [2, 3])
+def test_stress_is_energy_derivative(name, kin, d):
+    F, lam, mu = material_point(kin, d, 2)
+    assert stress_complex_step_error(materials.MATERIALS[name], F, lam, mu) < 1e-13
+
+
+@pytest.mark.parametrize("name,kin", MATS)
+@pytest.mark.parametrize("d", [2, 3])
+def test_tangent_is_stress_derivative(name, kin, d):
+    F, lam, mu = material_point(kin, d, 3)
+    rng = np.random.default_rng(4)
+    dF = rng.standard_normal(F.shape)
+    if kin == "small":
+        dF = sym(dF)
+    mat = materials.MATERIALS[name]
+    assert tangent_complex_step_error(mat, F, dF, lam, mu) < 1e-13
+    K = mat.tangent_tensor(F, lam, mu)
+    assert rel(np.einsum("...ijkl,...kl->...ij", K, dF), mat.tangent_apply(F, dF, lam, mu)) < 1e-14
+
+
+@pytest.mark.parametrize("name,kin", MATS)
+def test_tangent_matches_second_difference_of_energy(name, kin):
+    F, lam, mu = material_point(kin, 3, 5)
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal(F.shape)
+    B = rng.standard_normal(F.shape)
+    if kin == "small":
+        A, B = sym(A), sym(B)
+    mat = materials.MATERIALS[name]
+    h = 1e-4
+    psi = lambda X: mat.psi(X, lam, mu)  # noqa: E731
+    fd = (psi(F + h * A + h * B) - psi(F + h * A - h * B) - psi(F - h * A + h * B) + psi(F - h * A - h * B)) / (4 * h * h)
+    exact = np.einsum("...ij,...ij->...", A, mat.tangent_apply(F, B, lam, mu))
+    assert rel(fd, exact) < 1e-7
+
+
+def test_neohookean_reduces_to_linear_elastic_at_identity():
+    rng = np.random.default_rng(7)
+    lam, mu = 1.7, 0.9
+    I = np.eye(3)[None]
+    dE = sym(rng.standard_normal((4, 3, 3)))
+    W = rng.standard_normal((4, 3, 3))
+    W = W - np.swapaxes(W, -1, -2)
+    nh, le = materials.NeoHookean, materials.LinearElastic
+    assert np.abs(nh.stress(np.repeat(I, 4, 0), lam, mu)).max() < 1e-15
+    assert rel(nh.tangent_apply(np.repeat(I, 4, 0), dE, lam, mu), le.tangent_apply(dE, dE, lam, mu)) < 1e-15
+    assert np.abs(nh.tangent_apply(np.repeat(I, 4, 0), W, lam, mu)).max() < 1e-14
+
+
+def test_linear_elastic_modulus_convention():
+    """Plane-strain C_xxxx = lam + 2 mu (the paper's Table 1 matrix value about 4 for lam=2, mu=1)."""
+    C = closed_forms.isotropic_matrix(2.0, 1.0, 2)
+    assert C[0, 0] == 4.0 and C[2, 2] == 1.0 and C[0, 1] == 2.0
+    psi = materials.LinearElastic.psi(np.array([[0.01, 0.0], [0.0, 0.0]]), 2.0, 1.0)
+    assert abs(float(psi) - 0.5 * 4.0 * 1e-4) < 1e-18
+
+
+# ----------------------------------------------------------------------------
+# solver: closed forms and invariants
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(6, 7), (4, 5, 6)])
+def test_homogeneous_medium_linear_elastic(shape):
+    d = len(shape)
+    lam, mu = 1.3, 0.7
+    p = newton_cg.Problem(shape, "linear_elastic", lam, mu)
+    rng = np.random.default_rng(8)
+    macro = 0.01 * rng.standard_normal(3 if d == 2 else 6)
+    r = newton_cg.solve(p, macro)
+    assert r["stats"]["cg_total"] == 0 and r["stats"]["newton"] == 0
+    Cm = closed_forms.isotropic_matrix(lam, mu, d)
+    assert rel(r["macro_stress"], Cm @ macro) < 1e-14
+    C, Cd, counts = newton_cg.homogenized_tangent(p, r["state"])
+    assert sum(counts) == 0
+    assert np.abs(C - Cm).max() < 1e-14 * np.abs(Cm).max()
+
+
+@pytest.mark.parametrize("shape", [(5, 5), (3, 4, 5)])
+def test_homogeneous_medium_neohookean(shape):
+    d = len(shape)
+    p = newton_cg.Problem(shape, "neo_hookean", 2.0, 1.0)
+    rng = np.random.default_rng(9)
+    Fbar = np.eye(d) + 0.05 * rng.standard_normal((d, d))
+    r = newton_cg.solve(p, Fbar.reshape(-1), n_increments=3)
+    assert r["stats"]["cg_total"] == 0
+    assert rel(r["macro_stress"], materials.NeoHookean.stress(Fbar, 2.0, 1.0).reshape(-1)) < 1e-13
+    C, _, counts = newton_cg.homogenized_tangent(p, r["state"])
+    assert sum(counts) == 0
+    K = materials.NeoHookean.tangent_tensor(Fbar, 2.0, 1.0).reshape(d * d, d * d)
+    assert np.abs(C - K).max() < 1e-13 * np.abs(K).max()
+
+
+def _two_phase(phase, table):
+    table = np.asarray(table, dtype=float)
+    return table[phase, 0], table[phase, 1]
+
+
+@pytest.mark.parametrize("case", ["2d_odd", "3d_even"])
+def test_laminate_exact(case):
+    if case == "2d_odd":
+        shape, axis, ids, normal = (5, 9), 1, [0, 0, 1, 1, 1, 0, 0, 1, 0], [1.0, 0.0]
+    else:
+        shape, axis, ids, normal = (4, 6, 4), 1, [0, 0, 1, 1, 1, 1], [0.0, 1.0, 0.0]
+    d = len(shape)
+    table = [[1.0, 0.8], [6.0, 4.0]]
+    phase = workloads.laminate(shape, axis, ids)
+    lam, mu = _two_phase(phase, table)
+    p = newton_cg.Problem(shape, "linear_elastic", lam, mu)
+    r = newton_cg.solve(p, np.zeros(3 if d == 2 else 6), tol_cg=1e-14)
+    C, Cd, _ = newton_cg.homogenized_tangent(p, r["state"], tol_cg=1e-14)
+    f1 = float(np.mean(np.asarray(ids) == 1))
+    ref = closed_forms.laminate([closed_forms.isotropic_tensor(*table[0], d), closed_forms.isotropic_tensor(*table[1], d)],
+                                [1 - f1, f1], normal)
+    assert np.abs(C - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(Cd - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape", [(12, 12), (6, 6, 6)])
+def test_voigt_reuss_bounds_and_symmetry(shape):
+    d = len(shape)
+    table = [[1.0, 1.0], [12.0, 9.0]]
+    phase = workloads.random_phases(shape, 2, 10)
+    lam, mu = _two_phase(phase, table)
+    p = newton_cg.Problem(shape, "linear_elastic", lam, mu)
+    r = newton_cg.solve(p, np.zeros(3 if d == 2 else 6))
+    C, Cd, _ = newton_cg.homogenized_tangent(p, r["state"], tol_cg=1e-12)
+    f1 = float(phase.mean())
+    CV, CR = closed_forms.voigt_reuss([closed_forms.isotropic_matrix(*table[0], d),
+                                       closed_forms.isotropic_matrix(*table[1], d)], [1 - f1, f1])
+    scale = np.abs(C).max()
+    assert np.abs(C - C.T).max() < 1e-12 * scale
+    assert np.linalg.eigvalsh(CV - C).min() > -1e-12 * scale
+    assert np.linalg.eigvalsh(C - CR).min() > -1e-12 * scale
+    # strictly inside for a genuinely heterogeneous cell
+    assert np.linalg.eigvalsh(CV - C).max() > 1e-3 * scale
+
+
+BRUTE = [
+    ("linear_elastic", (4, 4)), ("linear_elastic", (5, 5)), ("linear_elastic", (3, 3, 3)), ("linear_elastic", (4, 3, 4)),
+    ("neo_hookean", (4, 4)), ("neo_hookean", (5, 4)), ("neo_hookean", (3, 3, 3)), ("neo_hookean", (4, 4, 3)),
+    ("stvk", (5, 5)), ("stvk", (3, 4, 3)),
+]
+
+
+@pytest.mark.parametrize("material,shape", BRUTE)
+def test_newton_cg_matches_dense_displacement_solve(material, shape):
+    d = len(shape)
+    rng = np.random.default_rng(11)
+    table = [[1.0, 1.0], [4.0, 3.0]]
+    phase = workloads.random_phases(shape, 2, 12)
+    lam, mu = _two_phase(phase, table)
+    p = newton_cg.Problem(shape, material, lam, mu)
+    if p.kinematics == "small":
+        macro = 0.01 * rng.standard_normal(3 if d == 2 else 6)
+        ref_macro = newton_cg.macro_to_tensor(macro, "small", d)
+    else:
+        Fbar = np.eye(d) + 0.04 * rng.standard_normal((d, d))
+        macro = Fbar.reshape(-1)
+        ref_macro = Fbar
+    r = newton_cg.solve(p, macro, n_increments=2, tol_newton=1e-13, tol_cg=1e-14)
+    assert r["stats"]["status"] == "ok"
+    field = r["state"].field
+    brute = bruteforce.solve_displacement(p, ref_macro)
+    assert rel(field - ref_macro, brute - ref_macro) < 1e-11
+
+
+def test_small_and_finite_tangents_agree_at_identity():
+    shape = (4, 5, 3)
+    table = [[1.0, 1.0], [5.0, 2.0]]
+    phase = workloads.random_phases(shape, 2, 13)
+    lam, mu = _two_phase(phase, table)
+    pn = newton_cg.Problem(shape, "neo_hookean", lam, mu)
+    pl = newton_cg.Problem(shape, "linear_elastic", lam, mu)
+    rn = newton_cg.solve(pn, np.eye(3).reshape(-1))
+    rl = newton_cg.solve(pl, np.zeros(6))
+    Cn, _, _ = newton_cg.homogenized_tangent(pn, rn["state"], tol_cg=1e-13)
+    Cl, _, _ = newton_cg.homogenized_tangent(pl, rl["state"], tol_cg=1e-13)
+    C4 = Cn.reshape(3, 3, 3, 3)
+    U = newton_cg.macro_basis("small", 3)
+    Cs = np.array([[np.einsum("ij,ijkl,kl->", A, C4, B) for B in U] for A in U])
+    assert np.abs(Cs - Cl).max() < 1e-11 * np.abs(Cl).max()
+    W = np.array([[0.0, 1.0, -0.5], [-1.0, 0.0, 2.0], [0.5, -2.0, 0.0]])
+    assert np.abs(np.einsum("ijkl,kl->ij", C4, W)).max() < 1e-11 * np.abs(Cl).max()
+
+
+def test_equilibrium_and_compatibility_at_convergence():
+    shape = (8, 8, 8)
+    wl = workloads.workload_neohookean3d(n=8, correlation_length=2.0)
+    lam, mu = _two_phase(wl["phase"], wl["table"])
+    p = newton_cg.Problem(shape, "neo_hookean", lam, mu)
+    r = newton_cg.solve(p, wl["macro"], n_increments=2, tol_newton=1e-10, tol_cg=1e-10)
+    assert r["stats"]["status"] == "ok" and r["stats"]["newton"] >= 2
+    F = r["state"].field
+    Fbar = wl["macro"].reshape(3, 3)
+    P = p.stress(F)
+    assert np.linalg.norm(p.G(P)) <= 1e-9 * np.linalg.norm(P)
+    assert np.abs(F.reshape(-1, 3, 3).mean(axis=0) - Fbar).max() < 1e-14
+    assert rel(p.G(F - Fbar), F - Fbar) < 1e-13
+
+
+def test_cg_textbook_on_spd_matrix():
+    """The CG routine solves a small SPD system to its tolerance in at most n steps."""
+    rng = np.random.default_rng(14)
+    M = rng.standard_normal((12, 12))
+    A = M @ M.T + 12 * np.eye(12)
+    b = rng.standard_normal(12)
+    x, k, st = newton_cg.conjugate_gradient(lambda v: A @ v, b, 1e-13, 100)
+    assert st == "ok" and k <= 14
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_eshelby_dilute_estimate_and_table1():
+    """Stiff disk at 0.7 % area fraction, 199^2 (the paper's section 4.2.1).
+
+    Pinned to the dilute Eshelby estimate (first order in the fraction, so
+    agreement to 1e-3 is expected).  The paper's Table 1 numerical values sit
+    about 6e-3 above both the dilute estimate and this discretisation of a
+    0.7 % disk; they are checked as plausibility only (1e-2).
+    """
+    vals = {}
+    with open(os.path.join(GOLDEN, "eshelby_table1.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, ana, num = line.split()
+                vals[k] = (float(ana), float(num))
+    n = 199
+    phase = workloads.disk_of_area_fraction(n, 0.007)
+    lam, mu = _two_phase(phase, [[2.0, 1.0], [10.0, 5.0]])
+    p = newton_cg.Problem((n, n), "linear_elastic", lam, mu)
+    r = newton_cg.solve(p, np.array([1e-2, 1e-2, 0.0]), tol_cg=1e-8)
+    C, _, _ = newton_cg.homogenized_tangent(p, r["state"], tol_cg=1e-8)
+    dilute = closed_forms.eshelby_dilute_disk(2.0, 1.0, 10.0, 5.0, float(phase.mean()))
+    assert np.abs(C - dilute).max() < 1e-3
+    assert abs(C[0, 0] - vals["C_xxxx"][1]) < 1e-2
+    assert abs(C[1, 1] - vals["C_yyyy"][1]) < 1e-2
+    assert abs(C[2, 2] - vals["C_xyxy"][1]) < 1e-2
+
+
+# ----------------------------------------------------------------------------
+# the pins catch plausible mistakes (planted in the oracle, on the CPU)
+# ----------------------------------------------------------------------------
+def test_pins_detect_planted_mistakes(monkeypatch):
+    shape, lengths = (5, 6, 7), (1.0, 0.8, 1.2)
+
+    # transposed contraction in the finite-strain projection: (A^T n) (x) n
+    orig = spectral.project_modes
+
+    def transposed(Ahat, n, kin):
+        return orig(np.swapaxes(Ahat, -1, -2), n, kin)
+
+    monkeypatch.setattr(spectral, "project_modes", transposed)
+    assert projection_kernel_error(shape, lengths, "finite") > 1e-3
+    monkeypatch.setattr(spectral, "project_modes", orig)
+
+    # dropped the last term of the small-strain projection
+    def dropped(Ahat, n, kin):
+        An = np.einsum("...ij,...j->...i", Ahat, n)
+        return An[..., :, None] * n[..., None, :] + n[..., :, None] * An[..., None, :]
+
+    monkeypatch.setattr(spectral, "project_modes", dropped)
+    assert projection_gradient_error(shape, lengths, "small") > 1e-3
+    monkeypatch.setattr(spectral, "project_modes", orig)
+
+    # wrong sign in the Neo-Hookean tangent's last term
+    nh = materials.NeoHookean
+    F, lam, mu = material_point("finite", 3, 15)
+    dF = np.random.default_rng(16).standard_normal(F.shape)
+
+    def bad_tangent(F, dF, lam, mu):
+        L = np.asarray(lam)[..., None, None]
+        M = np.asarray(mu)[..., None, None]
+        Finv = np.linalg.inv(F)
+        FinvT = np.swapaxes(Finv, -1, -2)
+        lnJ = np.log(np.linalg.det(F))[..., None, None]
+        tr = np.einsum("...ij,...ji->...", Finv, dF)[..., None, None]
+        return M * dF + L * tr * FinvT + (L * lnJ - M) * (FinvT @ np.swapaxes(dF, -1, -2) @ FinvT)
+
+    monkeypatch.setattr(nh, "tangent_apply", staticmethod(bad_tangent))
+    assert tangent_complex_step_error(nh, F, dF, lam, mu) > 1e-3

@@ -1,0 +1,182 @@
+"""Benchmark: Newton-CG voxel-iterations/s of the Fourier-Galerkin solve at 128^3, FP64.
+
+One step = one full fft_homog_solve of the 3D finite-strain workload (compressible
+Neo-Hookean, 128^3 two-phase Gaussian-random-field cell, mu 1 vs 20, lam = 2 mu,
+F-bar = diag(1.05, 1, 1) in 10 load increments, Newton and CG tolerance 1e-10),
+starting from the undeformed state.  value = N * (CG iterations of all timed
+steps) / wall time of the timed steps, inputs resident in HBM.
+
+Prints one JSON line (rank 0, one GPU) with a ``roofline`` entry for the
+dominant kernel of the CG iteration (algorithmic bytes / average launch time,
+HIP events on the library's stream) and a ``cpu_baseline`` entry (the CPU
+oracle timed on a bounded sample of CG iterations of the same workload).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ["xfwd_cgop", "reduce_pq", "y_fwd", "outer_project", "y_inv", "xinv_cgupdate", "reduce_rr"]
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def algorithmic_bytes_per_voxel(c, N, Nh, material_reads_strain=True):
+    """HBM bytes per voxel each CG-iteration kernel must move at minimum (FP64)."""
+    f = 8.0 * c               # one packed field
+    s = 16.0 * c * Nh / N     # one half spectrum, per voxel
+    xfwd = 2 * f + (f if material_reads_strain else 0.0) + 1.0 + f + s   # r, p, F, phase in; p, spec out
+    mid = 2 * s
+    outer = 2 * s
+    xinv = s + 3 * f + 2 * f                                            # spec, x, p, r in; x, r out
+    return {"xfwd_cgop": xfwd, "reduce_pq": 0.0, "y_fwd": mid, "outer_project": outer, "y_inv": mid,
+            "xinv_cgupdate": xinv, "reduce_rr": 0.0}
+
+
+def cpu_oracle_sample(w, iters):
+    """Time `iters` CG iterations of the CPU oracle on the first load increment of the workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import newton_cg
+
+    shape = w["shape"]
+    tab = np.asarray(w["table"])
+    lam, mu = tab[w["phase"], 0], tab[w["phase"], 1]
+    prob = newton_cg.Problem(shape, w["material"], lam, mu)
+    d = len(shape)
+    Fbar = w["macro"].reshape(d, d)
+    F1 = np.eye(d) + (Fbar - np.eye(d)) / w["n_increments"]
+    with threadpool_limits(limits=1):
+        field = prob.uniform(F1)
+        b = prob.rhs(field)
+        t0 = time.perf_counter()
+        _, k, st = newton_cg.conjugate_gradient(lambda v: prob.operator(field, v), b, 0.0, iters)
+        t1 = time.perf_counter()
+    N = prob.N
+    return {"value": N * k / (t1 - t0), "unit": "voxel-iter/s", "cores": 1, "kind": "oracle",
+            "sample": "%d CG iterations (operator G*(K:p) + textbook CG update) of the CPU oracle on the "
+                      "first load increment of the same %s workload, single thread, %.1f s" % (k, w["name"], t1 - t0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="grid points per axis")
+    ap.add_argument("--timing-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--k-mode", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_03804_amd import workloads
+    from paper_2408_03804_amd.binding import FFTHomog
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    n = args.n
+    w = workloads.workload_neohookean3d(n=n)
+    shape = w["shape"]
+    N = n ** 3
+    c = 9
+    log("workload %s generated" % w["name"])
+    h = FFTHomog(shape, "finite", "neo_hookean", 2, device="cuda:0", tol_newton=1e-10, tol_cg=1e-10,
+                 max_newton=50, max_cg=20000, k_mode=args.k_mode)
+    h.set_material(w["phase"], w["table"])
+    ident = torch.zeros((9,) + shape, dtype=torch.float64, device="cuda:0")
+    ident[0] = ident[4] = ident[8] = 1.0
+    eye = np.eye(3).reshape(-1)
+
+    def step():
+        h.set_field(ident, eye)
+        S, psi, st = h.solve(w["macro"], w["n_increments"])
+        if st["status"] != "ok":
+            raise RuntimeError("solve failed: %s" % st["status"])
+        return S, psi, st
+
+    for i in range(args.warmup):
+        S, psi, st = step()
+        log("warmup %d: newton %d, cg %d, %.3f s" % (i, st["newton"], st["cg_total"], st["seconds"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_cg = 0
+    stats = []
+    for i in range(args.steps):
+        S, psi, st = step()
+        total_cg += st["cg_total"]
+        stats.append(st)
+        log("step %d: newton %d, cg %d, %.3f s" % (i, st["newton"], st["cg_total"], st["seconds"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = N * total_cg / wall
+
+    # per-kernel device time of one CG iteration at the converged state
+    ms = h.debug_time_cg(args.timing_iters)
+    log("kernel ms: " + ", ".join("%s %.4f" % (k, v) for k, v in zip(KERNELS, ms)))
+    Nh = (n // 2 + 1) * n * n
+    bpv = algorithmic_bytes_per_voxel(c, N, Nh, True)
+    dom = int(np.argmax(ms))
+    name = KERNELS[dom]
+    achieved = bpv[name] * N / (ms[dom] * 1e-3) / 1e9
+    cg_ms = float(np.sum(ms))
+    iter_bytes = sum(bpv.values()) * N
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel_ms": round(float(ms[dom]), 5),
+                "algorithmic_bytes_per_launch": int(bpv[name] * N),
+                "cg_iteration": {"ms": round(cg_ms, 5), "algorithmic_bytes": int(iter_bytes),
+                                 "achieved_GBs": round(iter_bytes / (cg_ms * 1e-3) / 1e9, 1),
+                                 "kernels_ms": {k: round(float(v), 5) for k, v in zip(KERNELS, ms)}}}
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle (%d CG iterations at %d^3)" % (args.cpu_iters, n))
+        cpu = cpu_oracle_sample(w, args.cpu_iters)
+        log("cpu oracle: %.3e voxel-iter/s" % cpu["value"])
+
+    out = {
+        "metric": "Newton-CG voxel-iters/s at 128^3 FP64",
+        "value": value,
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"] + ": 3D finite-strain compressible Neo-Hookean, %d^3 voxels, Gaussian "
+                   "random field (l=8 voxels) thresholded at 30%% stiff, mu 1 vs 20, lam=2mu, F-bar=diag(1.05,1,1) "
+                   "in 10 increments, Newton/CG tol 1e-10, tangent by dual-number JVP" % n,
+                   "grid": [n, n, n], "n_increments": w["n_increments"], "k_mode": "stored" if args.k_mode else "recompute",
+                   "cg_iterations_per_step": [s["cg_total"] for s in stats],
+                   "newton_iterations_per_step": [s["newton"] for s in stats]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

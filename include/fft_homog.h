@@ -1,0 +1,196 @@
+/*
+ * fft_homog.h -- C ABI of the MI355X (gfx950) Fourier-Galerkin homogenization library.
+ *
+ * The library solves the periodic cell problem of Pundir & Kammer,
+ * "Simplifying FFT-based methods for solid mechanics with automatic
+ * differentiation" (arXiv:2408.03804):
+ *
+ *   section 3, Fourier-Galerkin equilibrium:  IFFT( G-hat(xi) : FFT(sigma(eps)) ) = 0
+ *   Appendix A, Algorithm 1:                  Newton outer loop, conjugate-gradient inner loop
+ *   section 3.1 / 3.2:                        stress = d psi / d eps and the incremental stress
+ *                                             K : d eps obtained by differentiating the energy
+ *                                             (here: forward-mode dual numbers inside the kernels)
+ *   section 3.3:                              homogenized stress (voxel average) and homogenized
+ *                                             tangent C = d sigma-bar / d eps-bar
+ *
+ * All compute runs on one HIP device in FP64.  Every function returns an
+ * fft_homog_status code; nothing throws across the ABI.  The library never
+ * allocates device memory: the caller passes one device workspace whose size
+ * fft_homog_workspace_size() reports.
+ *
+ * Conventions
+ *   grid        n[0], n[1], n[2] points along x, y, z (2D: n[2] is ignored, taken as 1);
+ *               device fields are stored component-major [comp][z][y][x], x fastest.
+ *   macro load  small strain: Voigt order [11,22,33,23,13,12] with engineering shear
+ *               strains (2D plane strain: [11,22,12]);
+ *               finite strain: the deformation gradient F-bar, row-major 3x3 (2D: 2x2).
+ *   macro out   stress in the same order without factors (small) / first Piola-Kirchhoff
+ *               stress row-major (finite); tangent C_IJ = d out_I / d macro_J, row-major.
+ *   ncomp       number of macro components: 3 / 6 (small, 2D / 3D), 4 / 9 (finite).
+ */
+#ifndef FFT_HOMOG_H
+#define FFT_HOMOG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fft_homog_status {
+  FFT_HOMOG_OK = 0,
+  FFT_HOMOG_EINVAL = 1,       /* invalid argument or descriptor */
+  FFT_HOMOG_ENOTCONV = 2,     /* max_newton or max_cg reached; results and stats still written */
+  FFT_HOMOG_EDOMAIN = 3,      /* det F <= 0 or a non-finite stress in the constitutive law */
+  FFT_HOMOG_EBREAKDOWN = 4,   /* CG found <p, K:p> <= 0 (operator not positive definite) */
+  FFT_HOMOG_ESTATE = 5,       /* call order violated (e.g. tangent before a successful solve) */
+  FFT_HOMOG_EUNSUPPORTED = 6, /* grid size or option not supported by this build */
+  FFT_HOMOG_EDEVICE = 7,      /* HIP runtime error; see fft_homog_last_error() */
+  FFT_HOMOG_EWORKSPACE = 8    /* workspace too small or not 256-byte aligned */
+} fft_homog_status;
+
+enum { FFT_HOMOG_SMALL_STRAIN = 0, FFT_HOMOG_FINITE_STRAIN = 1 };
+
+/* Constitutive laws (energy densities; lam, mu per phase):
+ *   LINEAR_ELASTIC (small strain)   psi = lam/2 tr(eps)^2 + mu eps:eps
+ *   NEO_HOOKEAN    (finite strain)  psi = mu/2 (tr(F^T F) - 3) - mu ln J + lam/2 (ln J)^2
+ *   STVK           (finite strain)  psi = lam/2 tr(E)^2 + mu E:E,  E = (F^T F - I)/2
+ * 2D is plane strain (eps_33 = 0, F_33 = 1). */
+enum { FFT_HOMOG_LINEAR_ELASTIC = 0, FFT_HOMOG_NEO_HOOKEAN = 1, FFT_HOMOG_STVK = 2 };
+
+/* How the CG operator obtains K : p (section 3.2):
+ *   RECOMPUTE  forward-over-forward dual-number JVP of the stress at every CG iteration
+ *              (the paper's jvp variant; reads only the linearisation point)
+ *   STORED     K materialised once per Newton iteration (the linearize / stored-tangent
+ *              variant; ncomp(ncomp+1)/2 doubles per voxel) */
+enum { FFT_HOMOG_K_RECOMPUTE = 0, FFT_HOMOG_K_STORED = 1 };
+
+/* flags */
+#define FFT_HOMOG_FLAG_TANGENT 1u  /* size the workspace for the ncomp-RHS tangent solve */
+#define FFT_HOMOG_FLAG_DENSITY 2u  /* reserve a per-voxel density field (SIMP scaling) */
+
+enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_ENERGY = 2 };
+
+typedef struct fft_homog_desc {
+  int ndim;          /* 2 or 3 */
+  int n[3];          /* grid points along x, y, z; each 1..1024 with prime factors <= 61 */
+  double len[3];     /* cell edge lengths along x, y, z (> 0); wavevector xi = 2 pi k / len */
+  int kinematics;    /* FFT_HOMOG_SMALL_STRAIN or FFT_HOMOG_FINITE_STRAIN */
+  int material;      /* FFT_HOMOG_LINEAR_ELASTIC (small) or NEO_HOOKEAN / STVK (finite) */
+  int nphase;        /* 1..256 */
+  double tol_newton; /* Newton stop: ||dF||_2 / (sqrt(N) ||F-bar||_F) < tol_newton */
+  double tol_cg;     /* CG stop: ||r|| <= tol_cg ||b|| */
+  int max_newton;    /* per load increment */
+  int max_cg;        /* per linear solve */
+  int k_mode;        /* FFT_HOMOG_K_RECOMPUTE or FFT_HOMOG_K_STORED */
+  unsigned flags;    /* FFT_HOMOG_FLAG_* */
+} fft_homog_desc;
+
+#define FFT_HOMOG_MAX_RECORDED 256
+
+typedef struct fft_homog_stats {
+  int status;                 /* fft_homog_status of the call */
+  int increments;             /* load increments completed */
+  int newton_iterations;      /* Newton iterations (linear solves) performed */
+  int cg_iterations;          /* CG iterations summed over all linear solves */
+  double newton_residual;     /* last ||dF||_2 / (sqrt(N) ||F-bar||_F) */
+  double cg_residual;         /* last ||r|| / ||b|| of the last linear solve */
+  double seconds;             /* device time of the call (HIP events on the stream) */
+  int n_recorded;             /* entries of cg_per_newton written */
+  int cg_per_newton[FFT_HOMOG_MAX_RECORDED]; /* CG iterations of each Newton iteration */
+} fft_homog_stats;
+
+typedef struct fft_homog fft_homog_t;
+
+/* Size in bytes of the device workspace that fft_homog_create() needs for *d.
+ * Pure host call.  EINVAL for an invalid descriptor, EUNSUPPORTED for a grid
+ * size this build cannot transform. */
+int fft_homog_workspace_size(const fft_homog_desc* d, size_t* bytes);
+
+/* Create a solver instance.
+ *   dev_workspace  device pointer, 256-byte aligned, >= workspace_size bytes; owned by the
+ *                  caller, must outlive the handle and is not freed by fft_homog_destroy().
+ *   hip_stream     hipStream_t on which every kernel of this handle is enqueued (NULL = the
+ *                  default stream).
+ * The strain field starts at the reference state (eps = 0, F = I); the
+ * material starts as phase 0 everywhere with lam = mu = 0 until
+ * fft_homog_set_material() is called. */
+int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes, void* hip_stream,
+                     fft_homog_t** out);
+
+/* Microstructure (the two-phase RVEs of section 4: per-phase Lame parameters).
+ *   phase            device u8[N], layout [z][y][x]; copied into the workspace.
+ *   phase_lambda_mu  host f64[nphase][2] = (lam, mu) per phase.
+ *   density          device f64[N] or NULL; when given (requires FLAG_DENSITY), lam and mu of
+ *                    voxel v are scaled by density[v]^simp_p.
+ * EINVAL if a phase id is >= nphase (checked on the device before returning). */
+int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* phase_lambda_mu,
+                           const double* density, double simp_p);
+
+/* Newton-CG solve (Appendix A, Algorithm 1) from the current state to the macro load
+ * `macro` (host f64[ncomp]) in n_increments equal load steps; each step starts from the
+ * previous converged field shifted by the uniform macro increment.
+ * Outputs (host, each nullable): macro_stress f64[ncomp] = voxel average of the stress,
+ * energy = voxel average of psi, stats.  Synchronous.  Returns OK, ENOTCONV,
+ * EDOMAIN or EBREAKDOWN; on ENOTCONV the state and outputs are those reached. */
+int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, double* macro_stress,
+                    double* energy, fft_homog_stats* st);
+
+/* Homogenized tangent at the last converged state (section 3.3): host f64[ncomp][ncomp],
+ * C_IJ = < (E_I + x_I) : K : (E_J + x_J) > with x_I solving G*(K:x_I) = -G*(K:E_I) for the
+ * unit macro loads E_I; all ncomp linear solves run batched in the same launches.
+ * Requires FLAG_TANGENT and a prior solve that returned OK (else ESTATE). */
+int fft_homog_tangent(fft_homog_t* h, double* C, fft_homog_stats* st);
+
+/* Gradient of J = w_energy * psi-bar + w_stress : stress-bar with respect to the per-voxel
+ * density (SIMP scaling of set_material) at the last converged state.  grad_density is a
+ * device f64[N].  Requires FLAG_DENSITY and a prior successful solve. */
+int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, double* grad_density,
+                      fft_homog_stats* st);
+
+/* Copy a field of the current state to device memory dst:
+ *   STRAIN / STRESS: f64[d*d][N], full row-major tensor components (small strain expanded from
+ *                    the packed storage); ENERGY: f64[N]. */
+int fft_homog_get_field(fft_homog_t* h, int which, double* dst);
+
+/* Restart from a given state: src device f64[d*d][N] full tensors, macro host f64[ncomp] the
+ * macro load that state belongs to (its voxel average).  Small strain takes the symmetric part. */
+int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro);
+
+void fft_homog_destroy(fft_homog_t* h);
+const char* fft_homog_strerror(int status);
+const char* fft_homog_last_error(const fft_homog_t* h);
+
+/* ---- stage-level entry points (tests) --------------------------------------------------
+ * Device arrays in the internal packed layout [batch][c][z][y][x]: c = ncomp, small strain
+ * packed as Mandel components [11,22,33,sqrt2*23,sqrt2*13,sqrt2*12] (2D [11,22,sqrt2*12]),
+ * finite strain F row-major.  Half spectra are complex f64 pairs [batch][c][z][y][nx/2+1].
+ * batch <= ncomp when FLAG_TANGENT is set, else 1. */
+
+/* Per voxel at strain e: P = d psi/de, K:de and psi by dual numbers (section 3.1, 3.2). */
+int fft_homog_debug_constitutive(fft_homog_t* h, const double* e, const double* de, double* P,
+                                 double* KdE, double* psi);
+/* Unnormalised forward real-to-complex 3D (2D) DFT of each component. */
+int fft_homog_debug_rfft(fft_homog_t* h, const double* in, double* spec, int batch);
+/* Inverse of debug_rfft including the 1/N scaling. */
+int fft_homog_debug_irfft(fft_homog_t* h, const double* spec, double* out, int batch);
+/* out = G*in = IFFT(G-hat : FFT(in)) (section 3, projection operator). */
+int fft_homog_debug_project(fft_homog_t* h, const double* in, double* out, int batch);
+/* q = G*(K(eps_current) : p), the CG operator at the current state. */
+int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, int batch);
+
+/* Average device time (ms, HIP events on the handle's stream) of each kernel of one CG
+ * iteration (section 3 operator, Appendix A linear solve), measured over `iters` iterations
+ * of the linear solve G*(K:x) = -G*(K:E_1) at the current state, batch 1, with the
+ * convergence test disabled.  ms[7] receives, in launch order: x-pass forward (K:p and
+ * x-FFT), <p,K:p> reduction, y-pass forward, outer pass (z-FFT, G-hat, inverse z-FFT),
+ * y-pass inverse, x-pass inverse (inverse x-FFT and CG update), <r,r> reduction (2D grids
+ * report 0 for the y passes).  Leaves the strain state unchanged. */
+int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT_HOMOG_H */

@@ -1,0 +1,67 @@
+// Types shared by the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fh {
+
+constexpr int kMaxStages = 20;
+constexpr int kMaxC = 9;
+constexpr int kMaxAxis = 1024;
+constexpr int kThreads = 256;
+
+// Factorisation of one FFT axis into Stockham stages and its twiddle table
+// tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device memory, host-computed in
+// extended precision).
+struct AxisPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  const double2* tw;
+};
+
+// Grid geometry.  2D grids are stored with nz = 1; the "outer" axis is the
+// slowest non-trivial one (z in 3D, y in 2D) and the "mid" axis is y in 3D.
+struct Geom {
+  int ndim;
+  int c;       // packed components per voxel
+  int nx, ny, nz;
+  int nxh;     // nx/2 + 1 half-spectrum bins along x
+  int n_outer, n_mid;
+  long long N;   // voxels
+  long long Nh;  // half-spectrum bins per component
+  double ks[3];  // 2 pi / L along x, y, z
+  int small;     // small strain (Mandel packing) or finite strain
+};
+
+// Per-voxel Lame parameters: (lam, mu) = table[phase[v]] * density[v]^p.
+struct MatParams {
+  const uint8_t* phase;
+  const double* table;    // [nphase][2]
+  const double* density;  // nullable
+  double simp_p;
+};
+
+// CG bookkeeping of one right-hand side, kept on the device so alpha and beta
+// never leave it.  status: see CgStatus.
+struct CgState {
+  double rr;        // current <r, r>
+  double rr0;       // <b, b>
+  double pq;        // <p, K:p>
+  double alpha;
+  double beta;
+  double src2;      // squared norm of the field whose projection is the right-hand side
+  double tol;       // relative CG tolerance
+  double pad0;
+  int iters;
+  int status;
+  int first;        // next CG iteration starts with p = r
+  int max_iters;
+  int domain;       // constitutive domain error raised (det F <= 0 or non-finite stress)
+  int pad1[3];
+};
+
+enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_ZERO_RHS = 2, CG_BREAKDOWN = 3, CG_MAXIT = 4 };
+
+}  // namespace fh

@@ -1,0 +1,793 @@
+// Host driver of the C ABI declared in include/fft_homog.h.
+//
+// Owns no device memory: every buffer is a slice of the caller's workspace.
+// All kernels run on the stream given at create time; the host reads back only
+// the small per-right-hand-side CG records (every few CG iterations) and the
+// reduced scalars of the Newton loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fft_homog.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace fh;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxPhase = 256;
+constexpr int kResults = 128;
+constexpr int kChunk = 8;          // CG iterations enqueued between host checks
+constexpr size_t kLdsFft = 48 * 1024;
+constexpr size_t kLdsOuter = 64 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ncomp_of(int kin, int ndim) { return kin == FFT_HOMOG_SMALL_STRAIN ? (ndim == 3 ? 6 : 3) : ndim * ndim; }
+
+// Factor n into Stockham radices: 8, 4, 2 for powers of two, then 3, 5 and any
+// remaining prime factor (direct DFT stage).
+bool factorize(int n, int* radix, int* nst) {
+  int k = 0;
+  int m = n;
+  while (m % 8 == 0 && k < kMaxStages) { radix[k++] = 8; m /= 8; }
+  while (m % 4 == 0 && k < kMaxStages) { radix[k++] = 4; m /= 4; }
+  while (m % 2 == 0 && k < kMaxStages) { radix[k++] = 2; m /= 2; }
+  for (int p = 3; m > 1 && k < kMaxStages; p += 2) {
+    while (m % p == 0 && k < kMaxStages) { radix[k++] = p; m /= p; }
+  }
+  *nst = k;
+  return m == 1;
+}
+
+struct Layout {
+  size_t F, x, r, p, spec, kst, phase, density, table, tw[3], partials, state, results, flags, total;
+  int B, R, TXm, TXo, nblk_x, nblk_vox;
+  size_t n_partials, smem_max;
+};
+
+bool make_geom(const fft_homog_desc* d, Geom* g) {
+  g->ndim = d->ndim;
+  g->c = ncomp_of(d->kinematics, d->ndim);
+  g->nx = d->n[0];
+  g->ny = d->n[1];
+  g->nz = d->ndim == 3 ? d->n[2] : 1;
+  g->nxh = g->nx / 2 + 1;
+  g->n_outer = d->ndim == 3 ? g->nz : g->ny;
+  g->n_mid = d->ndim == 3 ? g->ny : 1;
+  g->N = (long long)g->nx * g->ny * g->nz;
+  g->Nh = (long long)g->nxh * g->ny * g->nz;
+  const double twopi = 6.283185307179586476925286766559;
+  for (int a = 0; a < 3; ++a) g->ks[a] = (a < d->ndim) ? twopi / d->len[a] : 0.0;
+  g->small = d->kinematics == FFT_HOMOG_SMALL_STRAIN;
+  return true;
+}
+
+int validate_desc(const fft_homog_desc* d) {
+  if (!d) return FFT_HOMOG_EINVAL;
+  if (d->ndim != 2 && d->ndim != 3) return FFT_HOMOG_EINVAL;
+  for (int a = 0; a < d->ndim; ++a) {
+    if (d->n[a] < 1) return FFT_HOMOG_EINVAL;
+    if (!(d->len[a] > 0.0) || !std::isfinite(d->len[a])) return FFT_HOMOG_EINVAL;
+    if (d->n[a] > kMaxAxis) return FFT_HOMOG_EUNSUPPORTED;
+  }
+  if (d->kinematics != FFT_HOMOG_SMALL_STRAIN && d->kinematics != FFT_HOMOG_FINITE_STRAIN) return FFT_HOMOG_EINVAL;
+  if (d->kinematics == FFT_HOMOG_SMALL_STRAIN && d->material != FFT_HOMOG_LINEAR_ELASTIC) return FFT_HOMOG_EINVAL;
+  if (d->kinematics == FFT_HOMOG_FINITE_STRAIN && d->material != FFT_HOMOG_NEO_HOOKEAN &&
+      d->material != FFT_HOMOG_STVK)
+    return FFT_HOMOG_EINVAL;
+  if (d->nphase < 1 || d->nphase > kMaxPhase) return FFT_HOMOG_EINVAL;
+  if (!(d->tol_newton > 0.0) || !(d->tol_cg > 0.0)) return FFT_HOMOG_EINVAL;
+  if (d->max_newton < 0 || d->max_cg < 0) return FFT_HOMOG_EINVAL;
+  if (d->k_mode != FFT_HOMOG_K_RECOMPUTE && d->k_mode != FFT_HOMOG_K_STORED) return FFT_HOMOG_EINVAL;
+  return FFT_HOMOG_OK;
+}
+
+int make_layout(const fft_homog_desc* d, Layout* L) {
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  Geom g;
+  make_geom(d, &g);
+  const int C = g.c;
+  for (int a = 0; a < d->ndim; ++a) {
+    int rad[kMaxStages], ns;
+    if (!factorize(d->n[a], rad, &ns)) return FFT_HOMOG_EUNSUPPORTED;
+  }
+  L->B = (d->flags & FFT_HOMOG_FLAG_TANGENT) ? C : 1;
+  const int rows = g.ny * g.nz;
+  // x pass: rows per block
+  int R = 0;
+  for (int r = 16; r >= 1; --r) {
+    if (r > rows && r > 1) continue;
+    if (xfwd_smem(g, r) <= kLdsFft && xinv_smem(g, r) <= kLdsFft) { R = r; break; }
+  }
+  if (R == 0) {
+    if (xfwd_smem(g, 1) <= kLdsMax && xinv_smem(g, 1) <= kLdsMax) R = 1;
+    else return FFT_HOMOG_EUNSUPPORTED;
+  }
+  L->R = R;
+  int TXm = 1;
+  for (int t = 16; t >= 1; --t) {
+    if (t > g.nxh && t > 1) continue;
+    if (mid_smem(g, t) <= kLdsFft) { TXm = t; break; }
+  }
+  if (mid_smem(g, TXm) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
+  L->TXm = TXm;
+  int TXo = 0;
+  for (int t = 16; t >= 1; --t) {
+    if (t > g.nxh && t > 1) continue;
+    if (outer_smem(g, t) <= kLdsOuter) { TXo = t; break; }
+  }
+  if (TXo == 0) {
+    if (outer_smem(g, 1) <= kLdsMax) TXo = 1;
+    else return FFT_HOMOG_EUNSUPPORTED;
+  }
+  L->TXo = TXo;
+  L->smem_max = std::max(std::max(xfwd_smem(g, R), xinv_smem(g, R)), std::max(mid_smem(g, TXm), outer_smem(g, TXo)));
+  L->nblk_x = (rows + R - 1) / R;
+  L->nblk_vox = (int)((g.N + kThreads - 1) / kThreads);
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t fld = (size_t)C * g.N * sizeof(double);
+  L->F = take(fld);
+  L->x = take(fld * L->B);
+  L->r = take(fld * L->B);
+  L->p = take(fld * L->B);
+  L->spec = take((size_t)L->B * C * g.Nh * sizeof(double2));
+  L->kst = take(d->k_mode == FFT_HOMOG_K_STORED ? (size_t)C * (C + 1) / 2 * g.N * sizeof(double) : 0);
+  L->phase = take((size_t)g.N);
+  L->density = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
+  L->table = take(2 * kMaxPhase * sizeof(double));
+  for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? (size_t)d->n[a] * sizeof(double2) : 0);
+  size_t np = (size_t)L->B * L->nblk_x;
+  np = std::max(np, (size_t)C * C * L->nblk_vox);
+  np = std::max(np, (size_t)(C + 1) * L->nblk_vox);
+  L->n_partials = np;
+  L->partials = take(np * sizeof(double));
+  L->state = take((size_t)L->B * sizeof(CgState));
+  L->results = take(kResults * sizeof(double));
+  L->flags = take(16 * sizeof(int));
+  L->total = off;
+  return FFT_HOMOG_OK;
+}
+
+}  // namespace
+
+struct fft_homog {
+  fft_homog_desc desc;
+  Geom g;
+  Layout L;
+  int matcode;
+  hipStream_t stream;
+  char* ws;
+  double *F, *x, *r, *p, *kst, *partials, *results, *table, *density;
+  double2* spec;
+  uint8_t* phase;
+  int* flags;
+  CgState* st;
+  AxisPlan plan[3];
+  MatParams mat;
+  double macro_cur[kMaxC];
+  bool solved_ok;
+  // pinned host mirror of the device records
+  CgState* h_st;
+  double* h_results;
+  int* h_flags;
+  hipEvent_t ev0, ev1;
+  std::string err;
+};
+
+namespace {
+
+int fail(fft_homog_t* h, int code, const char* msg) {
+  if (h) h->err = msg ? msg : "";
+  return code;
+}
+
+#define FH_CK(expr)                                                               \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) return fail(h, FFT_HOMOG_EDEVICE, hipGetErrorString(e_)); \
+  } while (0)
+
+XFwdArgs xfwd_args(fft_homog_t* h) {
+  XFwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = h->g;
+  a.px = h->plan[0];
+  a.R = h->L.R;
+  a.nblocks = h->L.nblk_x;
+  a.F = h->F;
+  a.Kst = h->kst;
+  a.spec = h->spec;
+  a.mat = h->mat;
+  a.st = h->st;
+  a.partials = h->partials;
+  return a;
+}
+
+XInvArgs xinv_args(fft_homog_t* h) {
+  XInvArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = h->g;
+  a.px = h->plan[0];
+  a.R = h->L.R;
+  a.nblocks = h->L.nblk_x;
+  a.spec = h->spec;
+  a.x = h->x;
+  a.r = h->r;
+  a.p = h->p;
+  a.st = h->st;
+  a.partials = h->partials;
+  a.scale = 1.0 / (double)h->g.N;
+  return a;
+}
+
+AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st) {
+  AxisArgs a;
+  a.g = h->g;
+  a.pl = h->plan[axis];
+  a.TX = TX;
+  a.spec = h->spec;
+  a.st = st;
+  return a;
+}
+
+// spectral part shared by every operator application: y, outer (+G-hat), y^-1
+int spectral_middle(fft_homog_t* h, int mode, int B, const CgState* st) {
+  if (h->g.ndim == 3 && mode != OUTER_INV) FH_CK(launch_mid(-1, axis_args(h, 1, h->L.TXm, st), B, h->stream));
+  FH_CK(launch_outer(mode, axis_args(h, h->g.ndim - 1, h->L.TXo, st), B, h->stream));
+  if (h->g.ndim == 3 && mode != OUTER_FWD) FH_CK(launch_mid(1, axis_args(h, 1, h->L.TXm, st), B, h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int upload_states(fft_homog_t* h, int B) {
+  for (int b = 0; b < B; ++b) {
+    CgState& s = h->h_st[b];
+    memset(&s, 0, sizeof(s));
+    s.tol = h->desc.tol_cg;
+    s.max_iters = h->desc.max_cg;
+    s.status = CG_RUNNING;
+  }
+  FH_CK(hipMemcpyAsync(h->st, h->h_st, B * sizeof(CgState), hipMemcpyHostToDevice, h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int read_states(fft_homog_t* h, int B) {
+  FH_CK(hipMemcpyAsync(h->h_st, h->st, B * sizeof(CgState), hipMemcpyDeviceToHost, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+// right-hand sides b = -G*(source) for B loads; leaves x = 0, r = b and the CG records initialised
+int rhs_chain(fft_homog_t* h, int prod, int B, const double* unit) {
+  int rc = upload_states(h, B);
+  if (rc) return rc;
+  XFwdArgs a = xfwd_args(h);
+  if (unit)
+    for (int k = 0; k < h->g.c; ++k) a.unit[k] = unit[k];
+  FH_CK(launch_xfwd(prod, h->matcode, a, B, h->stream));
+  FH_CK(launch_cg_reduce(RED_SRC, h->st, h->partials, h->L.nblk_x, B, h->stream));
+  rc = spectral_middle(h, OUTER_PROJECT, B, nullptr);
+  if (rc) return rc;
+  FH_CK(launch_xinv(CONS_RHS, xinv_args(h), B, h->stream));
+  FH_CK(launch_cg_reduce(RED_RHS, h->st, h->partials, h->L.nblk_x, B, h->stream));
+  return read_states(h, B);
+}
+
+// conjugate gradients on all running right-hand sides until none is running
+int cg_loop(fft_homog_t* h, int B) {
+  const int prod = h->desc.k_mode == FFT_HOMOG_K_STORED ? PROD_CGOP_STORED : PROD_CGOP;
+  XFwdArgs a = xfwd_args(h);
+  a.in = h->r;
+  a.p = h->p;
+  XInvArgs ai = xinv_args(h);
+  for (;;) {
+    bool running = false;
+    int done = 1 << 30;
+    for (int b = 0; b < B; ++b)
+      if (h->h_st[b].status == CG_RUNNING) {
+        running = true;
+        done = std::min(done, h->h_st[b].iters);
+      }
+    if (!running) return FFT_HOMOG_OK;
+    int m = std::min(kChunk, std::max(1, h->desc.max_cg - done));
+    for (int i = 0; i < m; ++i) {
+      FH_CK(launch_xfwd(prod, h->matcode, a, B, h->stream));
+      FH_CK(launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, h->stream));
+      int rc = spectral_middle(h, OUTER_PROJECT, B, h->st);
+      if (rc) return rc;
+      FH_CK(launch_xinv(CONS_CGUPD, ai, B, h->stream));
+      FH_CK(launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, h->stream));
+    }
+    int rc = read_states(h, B);
+    if (rc) return rc;
+  }
+}
+
+void to_packed(const fft_homog_t* h, const double* macro, double* out) {
+  const int C = h->g.c;
+  const double h2 = 0.70710678118654752440;
+  for (int k = 0; k < C; ++k) out[k] = macro[k];
+  if (h->g.small)
+    for (int k = h->g.ndim; k < C; ++k) out[k] = macro[k] * h2;
+}
+
+void from_packed_stress(const fft_homog_t* h, const double* s, double* out) {
+  const int C = h->g.c;
+  const double h2 = 0.70710678118654752440;
+  for (int k = 0; k < C; ++k) out[k] = s[k];
+  if (h->g.small)
+    for (int k = h->g.ndim; k < C; ++k) out[k] = s[k] * h2;
+}
+
+void unit_loads(const fft_homog_t* h, double* unit) {
+  const double h2 = 0.70710678118654752440;
+  for (int k = 0; k < h->g.c; ++k) unit[k] = (h->g.small && k >= h->g.ndim) ? h2 : 1.0;
+}
+
+int reduce_to_host(fft_homog_t* h, int nslots, int nblocks) {
+  FH_CK(launch_reduce_slots(h->partials, nslots, nblocks, h->results, h->stream));
+  FH_CK(hipMemcpyAsync(h->h_results, h->results, nslots * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// public API
+// =============================================================================
+extern "C" {
+
+int fft_homog_workspace_size(const fft_homog_desc* d, size_t* bytes) {
+  if (!bytes) return FFT_HOMOG_EINVAL;
+  Layout L;
+  int rc = make_layout(d, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes, void* hip_stream,
+                     fft_homog_t** out) {
+  if (!out) return FFT_HOMOG_EINVAL;
+  *out = nullptr;
+  Layout L;
+  int rc = make_layout(d, &L);
+  if (rc) return rc;
+  if (!dev_workspace || bytes < L.total || ((uintptr_t)dev_workspace % kAlign) != 0) return FFT_HOMOG_EWORKSPACE;
+
+  fft_homog_t* h = new fft_homog();
+  h->desc = *d;
+  make_geom(d, &h->g);
+  h->L = L;
+  h->matcode = 2 * d->material + (d->ndim - 2);
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char*)dev_workspace;
+  h->F = (double*)(h->ws + L.F);
+  h->x = (double*)(h->ws + L.x);
+  h->r = (double*)(h->ws + L.r);
+  h->p = (double*)(h->ws + L.p);
+  h->spec = (double2*)(h->ws + L.spec);
+  h->kst = d->k_mode == FFT_HOMOG_K_STORED ? (double*)(h->ws + L.kst) : nullptr;
+  h->phase = (uint8_t*)(h->ws + L.phase);
+  h->density = (d->flags & FFT_HOMOG_FLAG_DENSITY) ? (double*)(h->ws + L.density) : nullptr;
+  h->table = (double*)(h->ws + L.table);
+  h->partials = (double*)(h->ws + L.partials);
+  h->st = (CgState*)(h->ws + L.state);
+  h->results = (double*)(h->ws + L.results);
+  h->flags = (int*)(h->ws + L.flags);
+  h->solved_ok = false;
+  for (int k = 0; k < kMaxC; ++k) h->macro_cur[k] = 0.0;
+  if (!h->g.small)
+    for (int i = 0; i < d->ndim; ++i) h->macro_cur[i * d->ndim + i] = 1.0;
+
+  h->h_st = nullptr;
+  if (hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + kResults * sizeof(double) + 64, 0) != hipSuccess) {
+    delete h;
+    return FFT_HOMOG_EDEVICE;
+  }
+  h->h_results = (double*)((char*)h->h_st + L.B * sizeof(CgState));
+  h->h_flags = (int*)(h->h_results + kResults);
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    hipHostFree(h->h_st);
+    delete h;
+    return FFT_HOMOG_EDEVICE;
+  }
+
+  // twiddle tables, computed in extended precision and rounded once
+  for (int a = 0; a < d->ndim; ++a) {
+    const int n = d->n[a];
+    std::vector<double2> tw(n);
+    for (int m = 0; m < n; ++m) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
+      tw[m] = make_double2((double)cosl(ang), (double)-sinl(ang));
+    }
+    double2* dtw = (double2*)(h->ws + L.tw[a]);
+    AxisPlan& pl = h->plan[a];
+    pl.n = n;
+    factorize(n, pl.radix, &pl.nstages);
+    pl.tw = dtw;
+    if (hipMemcpyAsync(dtw, tw.data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      fft_homog_destroy(h);
+      return FFT_HOMOG_EDEVICE;
+    }
+  }
+  if (h->g.ndim == 2) h->plan[2] = h->plan[1];
+
+  std::vector<double> zeros(2 * kMaxPhase, 0.0);
+  if (hipMemcpyAsync(h->table, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipMemsetAsync(h->phase, 0, (size_t)h->g.N, h->stream) != hipSuccess ||
+      launch_init_reference(h->F, h->g, h->stream) != hipSuccess ||
+      set_smem_limits(h->g, h->matcode, L.smem_max) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+    fft_homog_destroy(h);
+    return FFT_HOMOG_EDEVICE;
+  }
+  h->mat.phase = h->phase;
+  h->mat.table = h->table;
+  h->mat.density = nullptr;
+  h->mat.simp_p = 0.0;
+  *out = h;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* lm, const double* density,
+                           double simp_p) {
+  if (!h || !phase || !lm) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (density && !h->density) return fail(h, FFT_HOMOG_EINVAL, "density given but FLAG_DENSITY not set");
+  for (int k = 0; k < 2 * h->desc.nphase; ++k)
+    if (!std::isfinite(lm[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite phase table entry");
+  FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)h->g.N, hipMemcpyDeviceToDevice, h->stream));
+  FH_CK(hipMemcpyAsync(h->table, lm, 2 * h->desc.nphase * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (density) FH_CK(hipMemcpyAsync(h->density, density, (size_t)h->g.N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  h->mat.density = density ? h->density : nullptr;
+  h->mat.simp_p = simp_p;
+  h->h_flags[0] = 0;
+  FH_CK(hipMemcpyAsync(h->flags, h->h_flags, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  FH_CK(launch_check_phase(h->phase, h->g.N, h->desc.nphase, h->flags, h->stream));
+  FH_CK(hipMemcpyAsync(h->h_flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  h->solved_ok = false;
+  if (h->h_flags[0]) return fail(h, FFT_HOMOG_EINVAL, "phase id >= nphase");
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, double* macro_stress, double* energy,
+                    fft_homog_stats* stats) {
+  if (!h || !macro || n_increments < 1) return fail(h, FFT_HOMOG_EINVAL, "bad solve arguments");
+  const int C = h->g.c;
+  for (int k = 0; k < C; ++k)
+    if (!std::isfinite(macro[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite macro load");
+  fft_homog_stats S;
+  memset(&S, 0, sizeof(S));
+  FH_CK(hipEventRecord(h->ev0, h->stream));
+
+  double target[kMaxC], start[kMaxC], prev[kMaxC], cur[kMaxC], delta[kMaxC];
+  to_packed(h, macro, target);
+  for (int k = 0; k < C; ++k) start[k] = prev[k] = h->macro_cur[k];
+  const double sqrtN = std::sqrt((double)h->g.N);
+  int status = FFT_HOMOG_OK;
+  h->solved_ok = false;
+
+  for (int n = 1; n <= n_increments && status == FFT_HOMOG_OK; ++n) {
+    const double f = (double)n / (double)n_increments;
+    double mn = 0.0;
+    for (int k = 0; k < C; ++k) {
+      cur[k] = start[k] + f * (target[k] - start[k]);
+      delta[k] = cur[k] - prev[k];
+      prev[k] = cur[k];
+      mn += cur[k] * cur[k];
+    }
+    mn = std::sqrt(mn);
+    FH_CK(launch_shift(h->F, delta, h->g, h->stream));
+    for (int k = 0; k < C; ++k) h->macro_cur[k] = cur[k];
+    int it = 0;
+    for (;;) {
+      int rc = rhs_chain(h, PROD_STRESS, 1, nullptr);
+      if (rc) return rc;
+      const CgState& cs = h->h_st[0];
+      if (cs.domain) { status = FFT_HOMOG_EDOMAIN; break; }
+      if (cs.status == CG_ZERO_RHS) break;
+      if (it >= h->desc.max_newton) { status = FFT_HOMOG_ENOTCONV; break; }
+      if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+      rc = cg_loop(h, 1);
+      if (rc) return rc;
+      const CgState& ce = h->h_st[0];
+      if (S.n_recorded < FFT_HOMOG_MAX_RECORDED) S.cg_per_newton[S.n_recorded++] = ce.iters;
+      S.cg_iterations += ce.iters;
+      S.cg_residual = ce.rr0 > 0 ? std::sqrt(ce.rr / ce.rr0) : 0.0;
+      if (ce.status == CG_BREAKDOWN) { status = FFT_HOMOG_EBREAKDOWN; break; }
+      if (ce.status == CG_MAXIT) { status = FFT_HOMOG_ENOTCONV; break; }
+      FH_CK(launch_update(h->F, h->x, h->partials, h->L.nblk_vox, h->g, h->stream));
+      rc = reduce_to_host(h, 1, h->L.nblk_vox);
+      if (rc) return rc;
+      ++it;
+      S.newton_iterations++;
+      const double res = std::sqrt(h->h_results[0]) / (sqrtN * mn);
+      S.newton_residual = res;
+      if (res < h->desc.tol_newton) break;
+    }
+    if (status == FFT_HOMOG_OK) S.increments = n;
+  }
+
+  if (status != FFT_HOMOG_EDOMAIN) {
+    FH_CK(launch_homogenize(h->matcode, h->F, h->mat, h->partials, h->L.nblk_vox, h->g, h->st, h->stream));
+    int rc = reduce_to_host(h, C + 1, h->L.nblk_vox);
+    if (rc) return rc;
+    double sbar[kMaxC];
+    for (int k = 0; k < C; ++k) sbar[k] = h->h_results[k] / (double)h->g.N;
+    if (macro_stress) from_packed_stress(h, sbar, macro_stress);
+    if (energy) *energy = h->h_results[C] / (double)h->g.N;
+  }
+  FH_CK(hipEventRecord(h->ev1, h->stream));
+  FH_CK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  S.seconds = ms * 1e-3;
+  S.status = status;
+  h->solved_ok = status == FFT_HOMOG_OK;
+  if (stats) *stats = S;
+  if (status != FFT_HOMOG_OK) {
+    h->err = status == FFT_HOMOG_EDOMAIN ? "det F <= 0 or non-finite stress"
+             : status == FFT_HOMOG_EBREAKDOWN ? "CG breakdown: <p, K:p> <= 0"
+                                              : "iteration limit reached";
+  }
+  return status;
+}
+
+int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
+  if (!h || !Cout) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (!(h->desc.flags & FFT_HOMOG_FLAG_TANGENT)) return fail(h, FFT_HOMOG_ESTATE, "FLAG_TANGENT not set at create");
+  if (!h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
+  const int C = h->g.c;
+  fft_homog_stats S;
+  memset(&S, 0, sizeof(S));
+  FH_CK(hipEventRecord(h->ev0, h->stream));
+  double unit[kMaxC];
+  unit_loads(h, unit);
+  int rc = rhs_chain(h, PROD_TRHS, C, unit);
+  if (rc) return rc;
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+  rc = cg_loop(h, C);
+  if (rc) return rc;
+  int status = FFT_HOMOG_OK;
+  for (int b = 0; b < C; ++b) {
+    const CgState& s = h->h_st[b];
+    S.cg_iterations += s.iters;
+    if (S.n_recorded < FFT_HOMOG_MAX_RECORDED) S.cg_per_newton[S.n_recorded++] = s.iters;
+    if (s.status == CG_BREAKDOWN) status = FFT_HOMOG_EBREAKDOWN;
+    else if (s.status == CG_MAXIT && status == FFT_HOMOG_OK) status = FFT_HOMOG_ENOTCONV;
+  }
+  FH_CK(launch_tangent_matrix(h->matcode, h->F, h->x, unit, h->mat, h->partials, h->L.nblk_vox, h->g, h->stream));
+  rc = reduce_to_host(h, C * C, h->L.nblk_vox);
+  if (rc) return rc;
+  for (int k = 0; k < C * C; ++k) Cout[k] = h->h_results[k] / (double)h->g.N;
+  FH_CK(hipEventRecord(h->ev1, h->stream));
+  FH_CK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  S.seconds = ms * 1e-3;
+  S.status = status;
+  if (stats) *stats = S;
+  return status;
+}
+
+int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, double* grad_density,
+                      fft_homog_stats* st) {
+  (void)w_stress;
+  (void)w_energy;
+  (void)grad_density;
+  (void)st;
+  return fail(h, FFT_HOMOG_EUNSUPPORTED, "adjoint not built");
+}
+
+int fft_homog_get_field(fft_homog_t* h, int which, double* dst) {
+  if (!h || !dst) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (which == FFT_HOMOG_FIELD_STRAIN) {
+    FH_CK(launch_expand(h->F, dst, h->g, h->stream));
+  } else if (which == FFT_HOMOG_FIELD_STRESS) {
+    FH_CK(launch_stress_field(h->matcode, h->F, h->mat, h->r, nullptr, h->g, h->stream));
+    FH_CK(launch_expand(h->r, dst, h->g, h->stream));
+  } else if (which == FFT_HOMOG_FIELD_ENERGY) {
+    FH_CK(launch_stress_field(h->matcode, h->F, h->mat, nullptr, dst, h->g, h->stream));
+  } else {
+    return fail(h, FFT_HOMOG_EINVAL, "unknown field");
+  }
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro) {
+  if (!h || !src || !macro) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  FH_CK(launch_pack(src, h->F, h->g, h->stream));
+  to_packed(h, macro, h->macro_cur);
+  FH_CK(hipStreamSynchronize(h->stream));
+  h->solved_ok = false;
+  return FFT_HOMOG_OK;
+}
+
+void fft_homog_destroy(fft_homog_t* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  else hipDeviceSynchronize();
+  if (h->h_st) hipHostFree(h->h_st);
+  hipEventDestroy(h->ev0);
+  hipEventDestroy(h->ev1);
+  delete h;
+}
+
+const char* fft_homog_strerror(int s) {
+  switch (s) {
+    case FFT_HOMOG_OK: return "ok";
+    case FFT_HOMOG_EINVAL: return "invalid argument";
+    case FFT_HOMOG_ENOTCONV: return "not converged (iteration limit)";
+    case FFT_HOMOG_EDOMAIN: return "constitutive domain error (det F <= 0 or non-finite stress)";
+    case FFT_HOMOG_EBREAKDOWN: return "CG breakdown (<p, K:p> <= 0)";
+    case FFT_HOMOG_ESTATE: return "invalid call order";
+    case FFT_HOMOG_EUNSUPPORTED: return "unsupported";
+    case FFT_HOMOG_EDEVICE: return "HIP runtime error";
+    case FFT_HOMOG_EWORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+const char* fft_homog_last_error(const fft_homog_t* h) { return h ? h->err.c_str() : ""; }
+
+// ---- stage-level entry points -------------------------------------------------
+static int check_batch(fft_homog_t* h, int batch) {
+  if (batch < 1 || batch > h->L.B) return fail(h, FFT_HOMOG_EINVAL, "batch out of range");
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_constitutive(fft_homog_t* h, const double* e, const double* de, double* P, double* KdE,
+                                 double* psi) {
+  if (!h || !e || !de || !P || !KdE || !psi) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  FH_CK(launch_debug_constitutive(h->matcode, e, de, P, KdE, psi, h->mat, h->g, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_rfft(fft_homog_t* h, const double* in, double* spec, int batch) {
+  if (!h || !in || !spec) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  XFwdArgs a = xfwd_args(h);
+  a.in = in;
+  FH_CK(launch_xfwd(PROD_IDENT, h->matcode, a, batch, h->stream));
+  rc = spectral_middle(h, OUTER_FWD, batch, nullptr);
+  if (rc) return rc;
+  FH_CK(hipMemcpyAsync(spec, h->spec, (size_t)batch * h->g.c * h->g.Nh * sizeof(double2), hipMemcpyDeviceToDevice,
+                       h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_irfft(fft_homog_t* h, const double* spec, double* out, int batch) {
+  if (!h || !spec || !out) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  FH_CK(hipMemcpyAsync(h->spec, spec, (size_t)batch * h->g.c * h->g.Nh * sizeof(double2), hipMemcpyDeviceToDevice,
+                       h->stream));
+  rc = spectral_middle(h, OUTER_INV, batch, nullptr);
+  if (rc) return rc;
+  XInvArgs a = xinv_args(h);
+  a.out = out;
+  FH_CK(launch_xinv(CONS_IDENT, a, batch, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_project(fft_homog_t* h, const double* in, double* out, int batch) {
+  if (!h || !in || !out) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  XFwdArgs a = xfwd_args(h);
+  a.in = in;
+  FH_CK(launch_xfwd(PROD_IDENT, h->matcode, a, batch, h->stream));
+  rc = spectral_middle(h, OUTER_PROJECT, batch, nullptr);
+  if (rc) return rc;
+  XInvArgs ai = xinv_args(h);
+  ai.out = out;
+  FH_CK(launch_xinv(CONS_IDENT, ai, batch, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, int batch) {
+  if (!h || !p || !q) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  // q = G*(K:p): run one CG-operator pass with r = p, first = 1 (p_dir = r)
+  rc = upload_states(h, batch);
+  if (rc) return rc;
+  const size_t bytes = (size_t)batch * h->g.c * h->g.N * sizeof(double);
+  FH_CK(hipMemcpyAsync(h->r, p, bytes, hipMemcpyDeviceToDevice, h->stream));
+  for (int b = 0; b < batch; ++b) h->h_st[b].first = 1;
+  FH_CK(hipMemcpyAsync(h->st, h->h_st, batch * sizeof(CgState), hipMemcpyHostToDevice, h->stream));
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+  XFwdArgs a = xfwd_args(h);
+  a.in = h->r;
+  a.p = h->p;
+  FH_CK(launch_xfwd(h->kst ? PROD_CGOP_STORED : PROD_CGOP, h->matcode, a, batch, h->stream));
+  rc = spectral_middle(h, OUTER_PROJECT, batch, nullptr);
+  if (rc) return rc;
+  XInvArgs ai = xinv_args(h);
+  ai.out = q;
+  FH_CK(launch_xinv(CONS_IDENT, ai, batch, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
+  if (!h || !ms || iters < 1) return fail(h, FFT_HOMOG_EINVAL, "bad arguments");
+  double unit[kMaxC];
+  unit_loads(h, unit);
+  int rc = rhs_chain(h, PROD_TRHS, 1, unit);
+  if (rc) return rc;
+  if (h->h_st[0].status == CG_ZERO_RHS) return fail(h, FFT_HOMOG_ESTATE, "zero right-hand side (homogeneous cell)");
+  // keep the solve running for exactly `iters` iterations
+  h->h_st[0].status = CG_RUNNING;
+  h->h_st[0].tol = 0.0;
+  h->h_st[0].max_iters = iters + 1;
+  FH_CK(hipMemcpyAsync(h->st, h->h_st, sizeof(CgState), hipMemcpyHostToDevice, h->stream));
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+  const int prod = h->kst ? PROD_CGOP_STORED : PROD_CGOP;
+  XFwdArgs a = xfwd_args(h);
+  a.in = h->r;
+  a.p = h->p;
+  XInvArgs ai = xinv_args(h);
+  const bool three = h->g.ndim == 3;
+  hipEvent_t ev[8];
+  for (int k = 0; k < 8; ++k) FH_CK(hipEventCreate(&ev[k]));
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  int status = FFT_HOMOG_OK;
+  for (int i = 0; i < iters && status == FFT_HOMOG_OK; ++i) {
+    hipError_t e = hipEventRecord(ev[0], h->stream);
+    if (e == hipSuccess) e = launch_xfwd(prod, h->matcode, a, 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+    if (e == hipSuccess && three) e = launch_mid(-1, axis_args(h, 1, h->L.TXm, h->st), 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], h->stream);
+    if (e == hipSuccess) e = launch_outer(OUTER_PROJECT, axis_args(h, h->g.ndim - 1, h->L.TXo, h->st), 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], h->stream);
+    if (e == hipSuccess && three) e = launch_mid(1, axis_args(h, 1, h->L.TXm, h->st), 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[5], h->stream);
+    if (e == hipSuccess) e = launch_xinv(CONS_CGUPD, ai, 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[6], h->stream);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, 1, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[7], h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[7]);
+    for (int k = 0; k < 7 && e == hipSuccess; ++k) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      acc[k] += t;
+    }
+    if (e != hipSuccess) status = fail(h, FFT_HOMOG_EDEVICE, hipGetErrorString(e));
+  }
+  for (int k = 0; k < 8; ++k) hipEventDestroy(ev[k]);
+  if (status) return status;
+  int rc2 = read_states(h, 1);
+  if (rc2) return rc2;
+  if (h->h_st[0].status != CG_RUNNING && h->h_st[0].status != CG_MAXIT)
+    return fail(h, FFT_HOMOG_ESTATE, "timed CG stopped early (breakdown)");
+  for (int k = 0; k < 7; ++k) ms[k] = acc[k] / iters;
+  return FFT_HOMOG_OK;
+}
+
+}  // extern "C"

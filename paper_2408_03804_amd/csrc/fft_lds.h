@@ -1,0 +1,224 @@
+// Batched complex FFT of many short sequences held in LDS (Stockham autosort,
+// mixed radix 2/3/4/5/8 plus a direct DFT for any other prime factor).
+//
+// Layout: `nseq` sequences of length n interleaved element-major, element i of
+// sequence s at buf[i * nseq + s].  Consecutive threads work on consecutive
+// sequences, so LDS reads and writes of a stage are contiguous across a wave
+// and the tiles loaded from HBM (kx fastest) need no transpose.
+//
+// Each stage reads one buffer and writes the other (ping-pong); the function
+// returns the buffer that holds the result.  Forward transforms use
+// exp(-2 pi i jk/n), inverse exp(+2 pi i jk/n), both unnormalised.
+#pragma once
+
+#include "common.h"
+
+namespace fh {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by DIR * i  (DIR = -1 forward, +1 inverse)
+template <int DIR>
+__device__ __forceinline__ double2 mul_i(double2 a) {
+  return DIR > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+template <int DIR>
+__device__ __forceinline__ double2 twiddle(const double2* tw, int idx) {
+  double2 w = tw[idx];
+  return DIR > 0 ? make_double2(w.x, -w.y) : w;
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(double2* v) {
+  double2 a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft3(double2* v) {
+  const double h = 0.86602540378443864676;  // sqrt(3)/2
+  double2 s = cadd(v[1], v[2]);
+  double2 d = csub(v[1], v[2]);
+  double2 m = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
+  double2 t = mul_i<DIR>(cscale(d, h));
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(m, t);
+  v[2] = csub(m, t);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(double2* v) {
+  double2 t0 = cadd(v[0], v[2]);
+  double2 t1 = csub(v[0], v[2]);
+  double2 t2 = cadd(v[1], v[3]);
+  double2 t3 = mul_i<DIR>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft5(double2* v) {
+  const double c1 = 0.30901699437494742410;   // cos(2 pi/5)
+  const double c2 = -0.80901699437494742410;  // cos(4 pi/5)
+  const double s1 = 0.95105651629515357212;   // sin(2 pi/5)
+  const double s2 = 0.58778525229247312917;   // sin(4 pi/5)
+  double2 b1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+  double2 b2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+  double2 a0 = v[0];
+  double2 m1 = make_double2(a0.x + c1 * b1.x + c2 * b2.x, a0.y + c1 * b1.y + c2 * b2.y);
+  double2 m2 = make_double2(a0.x + c2 * b1.x + c1 * b2.x, a0.y + c2 * b1.y + c1 * b2.y);
+  double2 n1 = mul_i<DIR>(make_double2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+  double2 n2 = mul_i<DIR>(make_double2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+  v[0] = cadd(a0, cadd(b1, b2));
+  v[1] = cadd(m1, n1);
+  v[4] = csub(m1, n1);
+  v[2] = cadd(m2, n2);
+  v[3] = csub(m2, n2);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft8(double2* v) {
+  const double r = 0.70710678118654752440;
+  double2 b[4], c[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    b[t] = cadd(v[t], v[t + 4]);
+    c[t] = csub(v[t], v[t + 4]);
+  }
+  // c[t] *= w8^t, w8 = exp(DIR 2 pi i / 8)
+  c[1] = make_double2(r * (c[1].x - DIR * c[1].y), r * (c[1].y + DIR * c[1].x));
+  c[2] = mul_i<DIR>(c[2]);
+  c[3] = make_double2(r * (-c[3].x - DIR * c[3].y), r * (-c[3].y + DIR * c[3].x));
+  dft4<DIR>(b);
+  dft4<DIR>(c);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    v[2 * t] = b[t];
+    v[2 * t + 1] = c[t];
+  }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_small(double2* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 5) dft5<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+}
+
+// One Stockham stage of radix R for all sequences.
+//   Ns: product of the radices already applied; stride = n / (Ns R).
+//   Butterfly j (0 <= j < n/R) of a sequence: inputs x[j + t n/R], twiddled by
+//   w_n^(t k stride) with k = j mod Ns, output to (j - k) R + k + t Ns.
+template <int R, int DIR>
+__device__ __forceinline__ void stage_small(const double2* __restrict__ src, double2* __restrict__ dst,
+                                            int nseq, int n, int Ns, const double2* __restrict__ tw) {
+  const int nb = n / R;
+  const int stride = n / (Ns * R);
+  const int total = nb * nseq;
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int j = w / nseq;
+    const int s = w - j * nseq;
+    const int k = j % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = src[(j + t * nb) * nseq + s];
+    if (Ns > 1) {
+#pragma unroll
+      for (int t = 1; t < R; ++t) v[t] = cmul(v[t], twiddle<DIR>(tw, t * k * stride));
+    }
+    dft_small<R, DIR>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) dst[(base + t * Ns) * nseq + s] = v[t];
+  }
+}
+
+// Generic radix (any factor, used for primes > 5): direct DFT reading the
+// untouched source buffer; w_R^q = tw[(q mod R) * n / R].
+template <int DIR>
+__device__ __forceinline__ void stage_generic(const double2* __restrict__ src, double2* __restrict__ dst,
+                                              int nseq, int n, int Ns, int R, const double2* __restrict__ tw) {
+  const int nb = n / R;
+  const int stride = n / (Ns * R);
+  const int rstep = n / R;
+  const int total = nb * R * nseq;  // one thread per output element
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int s = w % nseq;
+    const int jm = w / nseq;
+    const int m = jm % R;   // output index within the butterfly
+    const int j = jm / R;   // butterfly
+    const int k = j % Ns;
+    double2 acc = make_double2(0.0, 0.0);
+    int q = 0;  // (t * m) mod R
+    for (int t = 0; t < R; ++t) {
+      double2 x = src[(j + t * nb) * nseq + s];
+      if (Ns > 1 && t > 0) x = cmul(x, twiddle<DIR>(tw, t * k * stride));
+      acc = cadd(acc, cmul(x, twiddle<DIR>(tw, q * rstep)));
+      q += m;
+      if (q >= R) q -= R;
+    }
+    const int base = (j - k) * R + k;
+    dst[(base + m * Ns) * nseq + s] = acc;
+  }
+}
+
+// Full transform of `nseq` interleaved sequences; returns the buffer holding the
+// result (a or b).  Must be called by every thread of the block.
+template <int DIR>
+__device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl) {
+  const int n = pl.n;
+  double2* src = a;
+  double2* dst = b;
+  int Ns = 1;
+  for (int st = 0; st < pl.nstages; ++st) {
+    const int R = pl.radix[st];
+    switch (R) {
+      case 2: stage_small<2, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      case 3: stage_small<3, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      case 4: stage_small<4, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      case 5: stage_small<5, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      case 8: stage_small<8, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      default: stage_generic<DIR>(src, dst, nseq, n, Ns, R, pl.tw); break;
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// ---- deterministic block reduction (wave64 shuffles, fixed order) ------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  `sh` needs blockDim/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace fh

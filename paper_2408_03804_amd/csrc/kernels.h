@@ -1,0 +1,87 @@
+// Kernel launchers used by the host driver (all enqueue on the given stream).
+#pragma once
+
+#include "common.h"
+
+namespace fh {
+
+enum Producer { PROD_IDENT = 0, PROD_STRESS = 1, PROD_CGOP = 2, PROD_TRHS = 3, PROD_CGOP_STORED = 4 };
+enum Consumer { CONS_IDENT = 0, CONS_RHS = 1, CONS_CGUPD = 2 };
+enum OuterMode { OUTER_PROJECT = 0, OUTER_FWD = 1, OUTER_INV = 2 };
+enum Reduce { RED_SRC = 0, RED_RHS = 1, RED_PQ = 2, RED_RR = 3 };
+
+// x-axis forward pass: per-voxel producer, then real-to-complex FFT along x.
+struct XFwdArgs {
+  Geom g;
+  AxisPlan px;
+  int R;                 // rows (y,z lines) per block
+  int nblocks;           // blocks per right-hand side
+  const double* in;      // IDENT: field [B][c][N]; CGOP: residual r [B][c][N]
+  double* p;             // CGOP: search direction, updated in place
+  const double* F;       // linearisation point / strain [c][N]
+  const double* Kst;     // stored tangent [c(c+1)/2][N]
+  double2* spec;         // [B][c][Nh]
+  MatParams mat;
+  CgState* st;           // per right-hand side
+  double* partials;      // [B][nblocks]
+  double unit[kMaxC];    // TRHS: unit load b is unit[b] * e_b in the packed basis
+};
+
+// x-axis inverse pass: complex-to-real FFT along x, then per-voxel consumer.
+struct XInvArgs {
+  Geom g;
+  AxisPlan px;
+  int R;
+  int nblocks;
+  const double2* spec;
+  double* out;           // IDENT output [B][c][N]
+  double* x;             // CG solution [B][c][N]
+  double* r;             // CG residual [B][c][N]
+  const double* p;       // CG direction [B][c][N]
+  CgState* st;
+  double* partials;
+  double scale;          // 1 / N
+};
+
+// y (3D) or outer-axis pass over the half spectrum.
+struct AxisArgs {
+  Geom g;
+  AxisPlan pl;
+  int TX;                // kx bins per block
+  double2* spec;
+  const CgState* st;     // nullable: skip right-hand sides whose CG is not running
+};
+
+size_t xfwd_smem(const Geom& g, int R);
+size_t xinv_smem(const Geom& g, int R);
+size_t mid_smem(const Geom& g, int TX);
+size_t outer_smem(const Geom& g, int TX);
+
+hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s);
+hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s);
+hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s);
+hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s);
+hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s);
+
+// Newton-level and post-processing kernels.
+hipError_t launch_init_reference(double* F, const Geom& g, hipStream_t s);
+hipError_t launch_shift(double* F, const double* delta, const Geom& g, hipStream_t s);
+hipError_t launch_update(double* F, const double* x, double* partials, int nblocks, const Geom& g,
+                         hipStream_t s);
+hipError_t launch_homogenize(int mat, const double* F, MatParams m, double* partials, int nblocks,
+                             const Geom& g, CgState* st, hipStream_t s);
+hipError_t launch_tangent_matrix(int mat, const double* F, const double* X, const double* unit, MatParams m,
+                                 double* partials, int nblocks, const Geom& g, hipStream_t s);
+hipError_t launch_reduce_slots(const double* partials, int nslots, int nblocks, double* out, hipStream_t s);
+hipError_t launch_store_tangent(int mat, const double* F, MatParams m, double* Kst, const Geom& g,
+                                hipStream_t s);
+hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipStream_t s);
+hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s);
+hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* full_out, double* energy_out,
+                               const Geom& g, hipStream_t s);
+hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s);
+hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE,
+                                     double* psi, MatParams m, const Geom& g, hipStream_t s);
+hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes);
+
+}  // namespace fh

@@ -1,0 +1,981 @@
+// HIP kernels of the Fourier-Galerkin Newton-CG solve for gfx950 (FP64).
+//
+// One CG iteration (section 3 equilibrium operator, section 3.2 incremental
+// stress, Appendix A linear solve) is five passes over the data:
+//
+//   xfwd   per voxel: p = r + beta p, tau = K(F) : p by dual numbers, partial
+//          <p, tau>; real-to-complex FFT of tau along x (rows in LDS)
+//   mid    complex FFT along y of the half spectrum            (3D only)
+//   outer  FFT along the outer axis, G-hat(xi) : tau-hat for all components of
+//          each wavevector, inverse FFT along the outer axis
+//   mid    inverse FFT along y                                 (3D only)
+//   xinv   complex-to-real FFT along x, then x += alpha p, r -= alpha q and a
+//          partial <r, r>
+//
+// plus two one-block reductions that turn the partial sums into alpha and beta
+// on the device.  <p, q> is taken as <p, K:p>: p lies in the range of the
+// projection G (it is built from projected residuals) and G is self-adjoint, so
+// <p, G(K:p)> = <G p, K:p> = <p, K:p> in exact arithmetic, and the xinv pass
+// then needs neither q in memory nor a re-read of p for the dot product.
+#include "common.h"
+#include "fft_lds.h"
+#include "kernels.h"
+#include "materials.h"
+
+namespace fh {
+
+// matcode = 2 * material + (ndim - 2)
+#define FH_DISPATCH_MAT(matcode, MACRO) \
+  switch (matcode) {                    \
+    case 0: MACRO(MAT_LE, 2); break;    \
+    case 1: MACRO(MAT_LE, 3); break;    \
+    case 2: MACRO(MAT_NH, 2); break;    \
+    case 3: MACRO(MAT_NH, 3); break;    \
+    case 4: MACRO(MAT_STVK, 2); break;  \
+    case 5: MACRO(MAT_STVK, 3); break;  \
+    default: return hipErrorInvalidValue; \
+  }
+
+__device__ __forceinline__ void load_lame(const MatParams& m, long long v, double& lam, double& mu) {
+  const int ph = m.phase[v];
+  lam = m.table[2 * ph];
+  mu = m.table[2 * ph + 1];
+  if (m.density != nullptr) {
+    const double s = pow(m.density[v], m.simp_p);
+    lam *= s;
+    mu *= s;
+  }
+}
+
+__device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ============================================================================
+// x-axis forward pass
+// ============================================================================
+template <int PROD, int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  const int b = blockIdx.y;
+  if (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED) {
+    if (a.st[b].status != CG_RUNNING) return;
+  }
+  const Geom& g = a.g;
+  const int nx = g.nx;
+  const int rows = g.ny * g.nz;
+  const int row0 = blockIdx.x * a.R;
+  const int nr = min(a.R, rows - row0);
+  const int nseq = C * nr;
+  const int P = (nseq + 1) >> 1;
+  extern __shared__ double2 smem[];
+  double2* A = smem;
+  double2* Bf = smem + (size_t)nx * P;
+  __shared__ double red[kThreads / 64];
+
+  double beta = 0.0;
+  int first = 1;
+  if (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED) {
+    beta = a.st[b].beta;
+    first = a.st[b].first;
+  }
+  const long long N = g.N;
+  double acc = 0.0;
+  int bad = 0;
+
+  for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
+    const int r = t / nx;
+    const int x = t - r * nx;
+    const long long vox = (long long)(row0 + r) * nx + x;
+    double v[C];
+    if (PROD == PROD_IDENT) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) v[j] = a.in[((long long)b * C + j) * N + vox];
+    } else {
+      double lam, mu;
+      load_lame(a.mat, vox, lam, mu);
+      double e[C];
+      // the linear elastic energy is quadratic: K does not depend on the strain,
+      // so the tangent passes do not read it
+      const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE);
+#pragma unroll
+      for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
+      if (PROD == PROD_STRESS) {
+        if (MAT != MAT_LE) {
+          const double J = det_packed<NDIM>(e);
+          if (!(J > 0.0)) bad = 1;
+        }
+        stress_ad<MAT, NDIM>(e, lam, mu, v);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          acc += v[j] * v[j];
+          if (!isfinite(v[j])) bad = 1;
+        }
+      } else if (PROD == PROD_TRHS) {
+        double de[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) de[j] = (j == b) ? a.unit[b] : 0.0;
+        tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, v);
+#pragma unroll
+        for (int j = 0; j < C; ++j) acc += v[j] * v[j];
+      } else {  // CG operator
+        double pv[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const long long idx = ((long long)b * C + j) * N + vox;
+          const double rj = a.in[idx];
+          pv[j] = first ? rj : rj + beta * a.p[idx];
+          a.p[idx] = pv[j];
+        }
+        if (PROD == PROD_CGOP) {
+          tangent_jvp_ad<MAT, NDIM>(e, pv, lam, mu, v);
+        } else {
+          // stored symmetric tangent, upper triangle row by row
+#pragma unroll
+          for (int i = 0; i < C; ++i) v[i] = 0.0;
+          int idx = 0;
+#pragma unroll
+          for (int i = 0; i < C; ++i) {
+#pragma unroll
+            for (int j = i; j < C; ++j) {
+              const double k = a.Kst[(long long)idx * N + vox];
+              v[i] += k * pv[j];
+              if (j != i) v[j] += k * pv[i];
+              ++idx;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) acc += pv[j] * v[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int qr = j * nr + r;
+      double* d = reinterpret_cast<double*>(&A[x * P + (qr >> 1)]);
+      d[qr & 1] = v[j];
+    }
+  }
+  if (nseq & 1) {
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) A[x * P + P - 1].y = 0.0;
+  }
+  if (PROD == PROD_STRESS && bad) a.st[b].domain = 1;
+  __syncthreads();
+
+  const double2* res = fft_lds<-1>(A, Bf, P, a.px);
+
+  // separate the two real rows packed in each complex sequence
+  const int nxh = g.nxh;
+  for (int t = threadIdx.x; t < P * nxh; t += blockDim.x) {
+    const int q = t / nxh;
+    const int k = t - q * nxh;
+    const double2 zk = res[k * P + q];
+    const double2 zm = res[(k == 0 ? 0 : nx - k) * P + q];
+    const int qa = 2 * q;
+    const int ja = qa / nr;
+    const int ra = qa - ja * nr;
+    a.spec[((long long)b * C + ja) * g.Nh + (long long)(row0 + ra) * nxh + k] =
+        make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+    if (qa + 1 < nseq) {
+      const int jb = (qa + 1) / nr;
+      const int rb = (qa + 1) - jb * nr;
+      a.spec[((long long)b * C + jb) * g.Nh + (long long)(row0 + rb) * nxh + k] =
+          make_double2(0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x));
+    }
+  }
+
+  if (PROD != PROD_IDENT) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[(long long)b * a.nblocks + blockIdx.x] = s;
+  }
+}
+
+// ============================================================================
+// x-axis inverse pass
+// ============================================================================
+template <int CONS, int C>
+__global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
+  const int b = blockIdx.y;
+  if (CONS == CONS_CGUPD) {
+    if (a.st[b].status != CG_RUNNING) return;
+  }
+  const Geom& g = a.g;
+  const int nx = g.nx;
+  const int nxh = g.nxh;
+  const int rows = g.ny * g.nz;
+  const int row0 = blockIdx.x * a.R;
+  const int nr = min(a.R, rows - row0);
+  const int nseq = C * nr;
+  const int P = (nseq + 1) >> 1;
+  extern __shared__ double2 smem[];
+  double2* A = smem;
+  double2* Bf = smem + (size_t)nx * P;  // also holds the loaded half rows
+  double2* H = Bf;
+  __shared__ double red[kThreads / 64];
+
+  for (int t = threadIdx.x; t < nseq * nxh; t += blockDim.x) {
+    const int qr = t / nxh;
+    const int k = t - qr * nxh;
+    const int j = qr / nr;
+    const int r = qr - j * nr;
+    H[k * nseq + qr] = a.spec[((long long)b * C + j) * g.Nh + (long long)(row0 + r) * nxh + k];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < P * nx; t += blockDim.x) {
+    const int k = t / P;
+    const int q = t - k * P;
+    const int qa = 2 * q;
+    const bool hb = qa + 1 < nseq;
+    double2 z;
+    if (k < nxh) {
+      double2 ha = H[k * nseq + qa];
+      double2 hv = hb ? H[k * nseq + qa + 1] : make_double2(0.0, 0.0);
+      if (k == 0 || 2 * k == nx) {
+        ha.y = 0.0;
+        hv.y = 0.0;
+      }
+      z = make_double2(ha.x - hv.y, ha.y + hv.x);
+    } else {
+      const int m = nx - k;
+      const double2 ha = H[m * nseq + qa];
+      const double2 hv = hb ? H[m * nseq + qa + 1] : make_double2(0.0, 0.0);
+      z = make_double2(ha.x + hv.y, hv.x - ha.y);
+    }
+    A[k * P + q] = z;
+  }
+  __syncthreads();
+
+  const double2* res = fft_lds<+1>(A, Bf, P, a.px);
+
+  const long long N = g.N;
+  double alpha = 0.0;
+  if (CONS == CONS_CGUPD) alpha = a.st[b].alpha;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
+    const int r = t / nx;
+    const int x = t - r * nx;
+    const long long vox = (long long)(row0 + r) * nx + x;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int qr = j * nr + r;
+      const double* d = reinterpret_cast<const double*>(&res[x * P + (qr >> 1)]);
+      const double u = d[qr & 1] * a.scale;
+      const long long idx = ((long long)b * C + j) * N + vox;
+      if (CONS == CONS_IDENT) {
+        a.out[idx] = u;
+      } else if (CONS == CONS_RHS) {
+        a.r[idx] = -u;
+        a.x[idx] = 0.0;
+        acc += u * u;
+      } else {
+        const double pj = a.p[idx];
+        a.x[idx] += alpha * pj;
+        const double rn = a.r[idx] - alpha * u;
+        a.r[idx] = rn;
+        acc += rn * rn;
+      }
+    }
+  }
+  if (CONS != CONS_IDENT) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[(long long)b * a.nblocks + blockIdx.x] = s;
+  }
+}
+
+// ============================================================================
+// y-axis pass (3D): complex FFT of the half spectrum along y, in place
+// ============================================================================
+template <int DIR>
+__global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
+  const Geom& g = a.g;
+  const int b = blockIdx.z / g.c;
+  if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
+  const int kx0 = blockIdx.x * a.TX;
+  const int tw = min(a.TX, g.nxh - kx0);
+  const int ny = g.ny;
+  extern __shared__ double2 smem[];
+  double2* A = smem;
+  double2* Bf = smem + (size_t)ny * tw;
+  const long long base = (long long)blockIdx.z * g.Nh + (long long)blockIdx.y * ny * g.nxh + kx0;
+  for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
+    const int y = t / tw;
+    const int s = t - y * tw;
+    A[t] = a.spec[base + (long long)y * g.nxh + s];
+  }
+  __syncthreads();
+  const double2* res = fft_lds<DIR>(A, Bf, tw, a.pl);
+  for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
+    const int y = t / tw;
+    const int s = t - y * tw;
+    a.spec[base + (long long)y * g.nxh + s] = res[t];
+  }
+}
+
+// ============================================================================
+// outer-axis pass with the projection G-hat (section 3)
+// ============================================================================
+__device__ __forceinline__ double signed_freq(int k, int n, double scale) {
+  if (2 * k < n) return k * scale;
+  if (2 * k == n) return 0.0;  // Nyquist: zero wavevector component
+  return (k - n) * scale;
+}
+
+// finite strain: A -> (A n) (x) n on row-major d x d tensors
+template <int D>
+__device__ __forceinline__ void project_finite(double2* v, const double* nv) {
+  double2 an[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    an[i] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      an[i].x += v[i * D + j].x * nv[j];
+      an[i].y += v[i * D + j].y * nv[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[i * D + j] = make_double2(an[i].x * nv[j], an[i].y * nv[j]);
+}
+
+// small strain, Mandel packed: A -> n (x) (A n) + (A n) (x) n - (n.A.n) n (x) n
+template <int D>
+__device__ __forceinline__ void project_small(double2* v, const double* nv) {
+  const double r2 = 1.41421356237309504880;
+  const double h2 = 0.70710678118654752440;
+  double2 T[D][D];
+  if (D == 3) {
+    T[0][0] = v[0]; T[1][1] = v[1]; T[2][2] = v[2];
+    T[1][2] = T[2][1] = make_double2(h2 * v[3].x, h2 * v[3].y);
+    T[0][2] = T[2][0] = make_double2(h2 * v[4].x, h2 * v[4].y);
+    T[0][1] = T[1][0] = make_double2(h2 * v[5].x, h2 * v[5].y);
+  } else {
+    T[0][0] = v[0]; T[1][1] = v[1];
+    T[0][1] = T[1][0] = make_double2(h2 * v[2].x, h2 * v[2].y);
+  }
+  double2 an[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    an[i] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      an[i].x += T[i][j].x * nv[j];
+      an[i].y += T[i][j].y * nv[j];
+    }
+  }
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s.x += nv[i] * an[i].x;
+    s.y += nv[i] * an[i].y;
+  }
+  auto o = [&](int i, int j) {
+    return make_double2(an[i].x * nv[j] + nv[i] * an[j].x - s.x * nv[i] * nv[j],
+                        an[i].y * nv[j] + nv[i] * an[j].y - s.y * nv[i] * nv[j]);
+  };
+  if (D == 3) {
+    v[0] = o(0, 0); v[1] = o(1, 1); v[2] = o(2, 2);
+    double2 t;
+    t = o(1, 2); v[3] = make_double2(r2 * t.x, r2 * t.y);
+    t = o(0, 2); v[4] = make_double2(r2 * t.x, r2 * t.y);
+    t = o(0, 1); v[5] = make_double2(r2 * t.x, r2 * t.y);
+  } else {
+    v[0] = o(0, 0); v[1] = o(1, 1);
+    const double2 t = o(0, 1);
+    v[2] = make_double2(r2 * t.x, r2 * t.y);
+  }
+}
+
+template <int MODE, int SMALL, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
+  constexpr int C = SMALL ? (NDIM == 3 ? 6 : 3) : (NDIM == 3 ? 9 : 4);
+  const Geom& g = a.g;
+  const int b = blockIdx.z;
+  if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
+  const int kx0 = blockIdx.x * a.TX;
+  const int tw = min(a.TX, g.nxh - kx0);
+  const int mid = blockIdx.y;
+  const int n = g.n_outer;
+  const int cnt = n * tw;
+  extern __shared__ double2 smem[];
+  double2* D = smem;
+  double2* pong = smem + (size_t)C * cnt;
+  const long long ostride = (long long)g.n_mid * g.nxh;
+  const long long base0 = (long long)mid * g.nxh + kx0;
+
+  for (int t = threadIdx.x; t < C * cnt; t += blockDim.x) {
+    const int j = t / cnt;
+    const int rem = t - j * cnt;
+    const int o = rem / tw;
+    const int s = rem - o * tw;
+    D[t] = a.spec[((long long)b * C + j) * g.Nh + base0 + o * ostride + s];
+  }
+  __syncthreads();
+
+  if (MODE != OUTER_INV) {
+    for (int j = 0; j < C; ++j) {
+      double2* Dj = D + (size_t)j * cnt;
+      const double2* res = fft_lds<-1>(Dj, pong, tw, a.pl);
+      if (res != Dj) {
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) Dj[t] = res[t];
+        __syncthreads();
+      }
+    }
+  }
+
+  if (MODE == OUTER_PROJECT) {
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int o = t / tw;
+      const int s = t - o * tw;
+      double xi[NDIM];
+      xi[0] = signed_freq(kx0 + s, g.nx, g.ks[0]);
+      if (NDIM == 3) {
+        xi[1] = signed_freq(mid, g.ny, g.ks[1]);
+        xi[NDIM - 1] = signed_freq(o, g.nz, g.ks[2]);
+      } else {
+        xi[1] = signed_freq(o, g.ny, g.ks[1]);
+      }
+      double nrm2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < NDIM; ++i) nrm2 += xi[i] * xi[i];
+      double2 v[C];
+      if (nrm2 > 0.0) {
+        const double inv = 1.0 / sqrt(nrm2);
+        double nv[NDIM];
+#pragma unroll
+        for (int i = 0; i < NDIM; ++i) nv[i] = xi[i] * inv;
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = D[(size_t)j * cnt + t];
+        if (SMALL) project_small<NDIM>(v, nv);
+        else project_finite<NDIM>(v, nv);
+      } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) D[(size_t)j * cnt + t] = v[j];
+    }
+    __syncthreads();
+  }
+
+  if (MODE != OUTER_FWD) {
+    for (int j = 0; j < C; ++j) {
+      double2* Dj = D + (size_t)j * cnt;
+      const double2* res = fft_lds<+1>(Dj, pong, tw, a.pl);
+      if (res != Dj) {
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) Dj[t] = res[t];
+        __syncthreads();
+      }
+    }
+  }
+
+  for (int t = threadIdx.x; t < C * cnt; t += blockDim.x) {
+    const int j = t / cnt;
+    const int rem = t - j * cnt;
+    const int o = rem / tw;
+    const int s = rem - o * tw;
+    a.spec[((long long)b * C + j) * g.Nh + base0 + o * ostride + s] = D[t];
+  }
+}
+
+// ============================================================================
+// reductions of block partial sums (one block per right-hand side, fixed order)
+// ============================================================================
+template <int WHAT>
+__global__ void __launch_bounds__(kThreads) k_cg_reduce(CgState* st, const double* partials, int nblocks) {
+  __shared__ double red[kThreads / 64];
+  const int b = blockIdx.x;
+  CgState& S = st[b];
+  if ((WHAT == RED_PQ || WHAT == RED_RR) && S.status != CG_RUNNING) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[(long long)b * nblocks + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  if (WHAT == RED_SRC) {
+    S.src2 = s;
+  } else if (WHAT == RED_RHS) {
+    S.rr0 = s;
+    S.rr = s;
+    S.iters = 0;
+    S.first = 1;
+    S.beta = 0.0;
+    if (sqrt(s) <= 1e-13 * sqrt(S.src2)) S.status = CG_ZERO_RHS;
+    else if (sqrt(s) <= S.tol * sqrt(s)) S.status = CG_CONVERGED;
+    else if (S.max_iters <= 0) S.status = CG_MAXIT;
+    else S.status = CG_RUNNING;
+  } else if (WHAT == RED_PQ) {
+    S.pq = s;
+    if (!(s > 0.0)) S.status = CG_BREAKDOWN;
+    else S.alpha = S.rr / s;
+  } else {  // RED_RR
+    S.beta = s / S.rr;
+    S.rr = s;
+    S.iters += 1;
+    S.first = 0;
+    if (sqrt(s) <= S.tol * sqrt(S.rr0)) S.status = CG_CONVERGED;
+    else if (S.iters >= S.max_iters) S.status = CG_MAXIT;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_slots(const double* partials, int nblocks, double* out) {
+  __shared__ double red[kThreads / 64];
+  const int sl = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[(long long)sl * nblocks + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[sl] = s;
+}
+
+// ============================================================================
+// Newton-level and post-processing kernels (one voxel per thread)
+// ============================================================================
+struct Small9 {
+  double v[kMaxC];
+};
+
+__global__ void k_init_reference(double* F, Geom g) {
+  const long long N = g.N;
+  const long long tot = N * g.c;
+  const int d = g.ndim;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(i / N);
+    F[i] = (!g.small && (j / d) == (j % d)) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_shift(double* F, Small9 delta, Geom g) {
+  const long long N = g.N;
+  const long long tot = N * g.c;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x)
+    F[i] += delta.v[i / N];
+}
+
+__global__ void __launch_bounds__(kThreads) k_update(double* F, const double* x, double* partials, Geom g) {
+  __shared__ double red[kThreads / 64];
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (v < N) {
+    for (int j = 0; j < g.c; ++j) {
+      const double dx = x[j * N + v];
+      F[j * N + v] += dx;
+      acc += dx * dx;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// per-block sums of m values per thread, written to partials[slot][block]
+__device__ __forceinline__ void block_sum_many(const double* vals, int m, double* sh, double* partials,
+                                               int nblocks) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < m; ++k) {
+    const double w = wave_sum(vals[k]);
+    if (lane == 0) sh[k * nw + wid] = w;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[k * nw + w];
+    partials[(long long)k * nblocks + blockIdx.x] = s;
+  }
+}
+
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_homogenize(const double* F, MatParams m, double* partials,
+                                                         int nblocks, Geom g, CgState* st) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  __shared__ double sh[(C + 1) * (kThreads / 64)];
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double vals[C + 1];
+#pragma unroll
+  for (int k = 0; k <= C; ++k) vals[k] = 0.0;
+  if (v < N) {
+    double e[C], lam, mu;
+#pragma unroll
+    for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+    load_lame(m, v, lam, mu);
+    if (MAT != MAT_LE && !(det_packed<NDIM>(e) > 0.0)) st[0].domain = 1;
+    vals[C] = stress_ad<MAT, NDIM>(e, lam, mu, vals);
+  }
+  block_sum_many(vals, C + 1, sh, partials, nblocks);
+}
+
+// C_IJ partial sums: (E_I + x_I) . K : (E_J + x_J) per voxel
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_tangent_matrix(const double* F, const double* X, Small9 unit,
+                                                             MatParams m, double* partials, int nblocks, Geom g) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  __shared__ double sh[C * C * (kThreads / 64)];
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double vals[C * C];
+#pragma unroll
+  for (int k = 0; k < C * C; ++k) vals[k] = 0.0;
+  if (v < N) {
+    double e[C], lam, mu;
+    const bool need_e = MAT != MAT_LE;
+#pragma unroll
+    for (int j = 0; j < C; ++j) e[j] = need_e ? F[j * N + v] : 0.0;
+    load_lame(m, v, lam, mu);
+    for (int J = 0; J < C; ++J) {
+      double tJ[C], w[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) tJ[j] = X[((long long)J * C + j) * N + v] + (j == J ? unit.v[J] : 0.0);
+      tangent_jvp_ad<MAT, NDIM>(e, tJ, lam, mu, w);
+      for (int I = 0; I < C; ++I) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) s += (X[((long long)I * C + j) * N + v] + (j == I ? unit.v[I] : 0.0)) * w[j];
+        vals[I * C + J] = s;
+      }
+    }
+  }
+  block_sum_many(vals, C * C, sh, partials, nblocks);
+}
+
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_store_tangent(const double* F, MatParams m, double* Kst, Geom g) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], lam, mu;
+#pragma unroll
+  for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+  load_lame(m, v, lam, mu);
+  int idx = 0;
+  for (int i = 0; i < C; ++i) {
+    double de[C], col[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) de[j] = (j == i) ? 1.0 : 0.0;
+    tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, col);  // column i = row i (K symmetric)
+    for (int j = i; j < C; ++j) {
+      Kst[(long long)idx * N + v] = col[j];
+      ++idx;
+    }
+  }
+}
+
+// packed (Mandel / row-major F) -> full row-major d x d components
+__global__ void k_expand(const double* packed, double* full, Geom g) {
+  const long long N = g.N;
+  const int d = g.ndim;
+  const double h2 = 0.70710678118654752440;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double val;
+        if (!g.small) {
+          val = packed[(i * d + j) * N + v];
+        } else if (i == j) {
+          val = packed[i * N + v];
+        } else {
+          int k;
+          if (d == 2) k = 2;
+          else k = (i + j == 3) ? 3 : (i + j == 2 ? 4 : 5);  // (1,2)->3, (0,2)->4, (0,1)->5
+          val = h2 * packed[k * N + v];
+        }
+        full[(i * d + j) * N + v] = val;
+      }
+  }
+}
+
+__global__ void k_pack(const double* full, double* packed, Geom g) {
+  const long long N = g.N;
+  const int d = g.ndim;
+  const double r2 = 1.41421356237309504880;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    if (!g.small) {
+      for (int k = 0; k < d * d; ++k) packed[k * N + v] = full[k * N + v];
+    } else {
+      for (int i = 0; i < d; ++i) packed[i * N + v] = full[(i * d + i) * N + v];
+      auto sym = [&](int i, int j) { return 0.5 * (full[(i * d + j) * N + v] + full[(j * d + i) * N + v]); };
+      if (d == 2) {
+        packed[2 * N + v] = r2 * sym(0, 1);
+      } else {
+        packed[3 * N + v] = r2 * sym(1, 2);
+        packed[4 * N + v] = r2 * sym(0, 2);
+        packed[5 * N + v] = r2 * sym(0, 1);
+      }
+    }
+  }
+}
+
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_stress_field(const double* F, MatParams m, double* packed_out,
+                                                           double* energy_out, Geom g) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], P[C], lam, mu;
+#pragma unroll
+  for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+  load_lame(m, v, lam, mu);
+  const double psi = stress_ad<MAT, NDIM>(e, lam, mu, P);
+  if (packed_out != nullptr) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) packed_out[j * N + v] = P[j];
+  }
+  if (energy_out != nullptr) energy_out[v] = psi;
+}
+
+__global__ void k_check_phase(const uint8_t* phase, long long N, int nphase, int* flag) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x)
+    if (phase[v] >= nphase) flag[0] = 1;
+}
+
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_debug_constitutive(const double* e_in, const double* de_in, double* P,
+                                                                 double* KdE, double* psi, MatParams m, Geom g) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], de[C], p[C], k[C], lam, mu;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    e[j] = e_in[j * N + v];
+    de[j] = de_in[j * N + v];
+  }
+  load_lame(m, v, lam, mu);
+  const double ps = stress_and_jvp_ad<MAT, NDIM>(e, de, lam, mu, p, k);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    P[j * N + v] = p[j];
+    KdE[j * N + v] = k[j];
+  }
+  psi[v] = ps;
+}
+
+// ============================================================================
+// host launchers
+// ============================================================================
+size_t xfwd_smem(const Geom& g, int R) {
+  const int P = (g.c * R + 1) / 2;
+  return 2ull * g.nx * P * sizeof(double2);
+}
+size_t xinv_smem(const Geom& g, int R) {
+  const int P = (g.c * R + 1) / 2;
+  const size_t a = (size_t)g.nx * P;
+  size_t bsz = (size_t)g.nx * P;
+  const size_t h = (size_t)g.nxh * g.c * R;
+  if (h > bsz) bsz = h;
+  return (a + bsz) * sizeof(double2);
+}
+size_t mid_smem(const Geom& g, int TX) { return 2ull * g.ny * TX * sizeof(double2); }
+size_t outer_smem(const Geom& g, int TX) { return (size_t)(g.c + 1) * g.n_outer * TX * sizeof(double2); }
+
+static inline int nblk_rows(const Geom& g, int R) { return (g.ny * g.nz + R - 1) / R; }
+
+hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s) {
+  dim3 grid(nblk_rows(a.g, a.R), B);
+  const size_t sm = xfwd_smem(a.g, a.R);
+#define FH_L(M, D)                                                                                       \
+  switch (prod) {                                                                                        \
+    case PROD_IDENT: hipLaunchKernelGGL((k_xfwd<PROD_IDENT, M, D>), grid, dim3(kThreads), sm, s, a); break;   \
+    case PROD_STRESS: hipLaunchKernelGGL((k_xfwd<PROD_STRESS, M, D>), grid, dim3(kThreads), sm, s, a); break; \
+    case PROD_CGOP: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, M, D>), grid, dim3(kThreads), sm, s, a); break;     \
+    case PROD_TRHS: hipLaunchKernelGGL((k_xfwd<PROD_TRHS, M, D>), grid, dim3(kThreads), sm, s, a); break;     \
+    case PROD_CGOP_STORED:                                                                               \
+      hipLaunchKernelGGL((k_xfwd<PROD_CGOP_STORED, M, D>), grid, dim3(kThreads), sm, s, a); break;       \
+    default: return hipErrorInvalidValue;                                                                \
+  }
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
+  dim3 grid(nblk_rows(a.g, a.R), B);
+  const size_t sm = xinv_smem(a.g, a.R);
+#define FH_L(CC)                                                                                        \
+  switch (cons) {                                                                                       \
+    case CONS_IDENT: hipLaunchKernelGGL((k_xinv<CONS_IDENT, CC>), grid, dim3(kThreads), sm, s, a); break; \
+    case CONS_RHS: hipLaunchKernelGGL((k_xinv<CONS_RHS, CC>), grid, dim3(kThreads), sm, s, a); break;     \
+    case CONS_CGUPD: hipLaunchKernelGGL((k_xinv<CONS_CGUPD, CC>), grid, dim3(kThreads), sm, s, a); break; \
+    default: return hipErrorInvalidValue;                                                               \
+  }
+  switch (a.g.c) {
+    case 3: FH_L(3); break;
+    case 4: FH_L(4); break;
+    case 6: FH_L(6); break;
+    case 9: FH_L(9); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
+  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.nz, B * a.g.c);
+  const size_t sm = mid_smem(a.g, a.TX);
+  if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
+  else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s) {
+  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.n_mid, B);
+  const size_t sm = outer_smem(a.g, a.TX);
+#define FH_L(SM, D)                                                                                          \
+  switch (mode) {                                                                                            \
+    case OUTER_PROJECT: hipLaunchKernelGGL((k_outer<OUTER_PROJECT, SM, D>), grid, dim3(kThreads), sm, s, a); break; \
+    case OUTER_FWD: hipLaunchKernelGGL((k_outer<OUTER_FWD, SM, D>), grid, dim3(kThreads), sm, s, a); break;         \
+    case OUTER_INV: hipLaunchKernelGGL((k_outer<OUTER_INV, SM, D>), grid, dim3(kThreads), sm, s, a); break;         \
+    default: return hipErrorInvalidValue;                                                                    \
+  }
+  if (a.g.small) {
+    if (a.g.ndim == 3) { FH_L(1, 3) } else { FH_L(1, 2) }
+  } else {
+    if (a.g.ndim == 3) { FH_L(0, 3) } else { FH_L(0, 2) }
+  }
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s) {
+  switch (what) {
+    case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
+    case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
+    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
+    case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static inline dim3 vox_grid(const Geom& g) { return dim3((unsigned)((g.N + kThreads - 1) / kThreads)); }
+static inline dim3 stride_grid(long long work) {
+  long long b = (work + kThreads - 1) / kThreads;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t launch_init_reference(double* F, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_reference, stride_grid(g.N * g.c), dim3(kThreads), 0, s, F, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(double* F, const double* delta, const Geom& g, hipStream_t s) {
+  Small9 d;
+  for (int k = 0; k < kMaxC; ++k) d.v[k] = k < g.c ? delta[k] : 0.0;
+  hipLaunchKernelGGL(k_shift, stride_grid(g.N * g.c), dim3(kThreads), 0, s, F, d, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(double* F, const double* x, double* partials, int nblocks, const Geom& g, hipStream_t s) {
+  (void)nblocks;
+  hipLaunchKernelGGL(k_update, vox_grid(g), dim3(kThreads), 0, s, F, x, partials, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_homogenize(int mat, const double* F, MatParams m, double* partials, int nblocks, const Geom& g,
+                             CgState* st, hipStream_t s) {
+#define FH_L(M, D) hipLaunchKernelGGL((k_homogenize<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, m, partials, nblocks, g, st)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_matrix(int mat, const double* F, const double* X, const double* unit, MatParams m,
+                                 double* partials, int nblocks, const Geom& g, hipStream_t s) {
+  Small9 u;
+  for (int k = 0; k < kMaxC; ++k) u.v[k] = k < g.c ? unit[k] : 0.0;
+#define FH_L(M, D) \
+  hipLaunchKernelGGL((k_tangent_matrix<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, X, u, m, partials, nblocks, g)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_slots(const double* partials, int nslots, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_slots, dim3(nslots), dim3(kThreads), 0, s, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_tangent(int mat, const double* F, MatParams m, double* Kst, const Geom& g, hipStream_t s) {
+#define FH_L(M, D) hipLaunchKernelGGL((k_store_tangent<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, m, Kst, g)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, stride_grid(g.N), dim3(kThreads), 0, s, packed, full, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, stride_grid(g.N), dim3(kThreads), 0, s, full, packed, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* packed_out, double* energy_out,
+                               const Geom& g, hipStream_t s) {
+#define FH_L(M, D) \
+  hipLaunchKernelGGL((k_stress_field<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, m, packed_out, energy_out, g)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_phase, stride_grid(N), dim3(kThreads), 0, s, phase, N, nphase, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE, double* psi,
+                                     MatParams m, const Geom& g, hipStream_t s) {
+#define FH_L(M, D) \
+  hipLaunchKernelGGL((k_debug_constitutive<M, D>), vox_grid(g), dim3(kThreads), 0, s, e, de, P, KdE, psi, m, g)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
+// Raise the dynamic-LDS limit of the FFT kernels when a plan needs more than 64 KiB.
+hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  const int attr = (int)hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipSuccess;
+#define FH_SET(fn) \
+  if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), (hipFuncAttribute)attr, (int)bytes)
+#define FH_L(M, D)                                  \
+  FH_SET((k_xfwd<PROD_IDENT, M, D>));               \
+  FH_SET((k_xfwd<PROD_STRESS, M, D>));              \
+  FH_SET((k_xfwd<PROD_CGOP, M, D>));                \
+  FH_SET((k_xfwd<PROD_TRHS, M, D>));                \
+  FH_SET((k_xfwd<PROD_CGOP_STORED, M, D>));
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+#define FH_X(CC) FH_SET((k_xinv<CONS_IDENT, CC>)); FH_SET((k_xinv<CONS_RHS, CC>)); FH_SET((k_xinv<CONS_CGUPD, CC>));
+  switch (g.c) {
+    case 3: FH_X(3); break;
+    case 4: FH_X(4); break;
+    case 6: FH_X(6); break;
+    case 9: FH_X(9); break;
+    default: break;
+  }
+#undef FH_X
+  FH_SET((k_mid<-1>));
+  FH_SET((k_mid<1>));
+#define FH_O(SM, D) FH_SET((k_outer<OUTER_PROJECT, SM, D>)); FH_SET((k_outer<OUTER_FWD, SM, D>)); FH_SET((k_outer<OUTER_INV, SM, D>));
+  if (g.small) {
+    if (g.ndim == 3) { FH_O(1, 3) } else { FH_O(1, 2) }
+  } else {
+    if (g.ndim == 3) { FH_O(0, 3) } else { FH_O(0, 2) }
+  }
+#undef FH_O
+#undef FH_SET
+  return e;
+}
+
+}  // namespace fh

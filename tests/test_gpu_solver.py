@@ -1,0 +1,207 @@
+"""End-to-end parity of the HIP Newton-CG solve and tangent against the CPU oracle.
+
+Same seeded inputs on both sides.  Parity runs use a tight CG tolerance (1e-12)
+so that field differences reflect rounding, not truncation; fields are compared
+on the fluctuation (strain minus its mean) and on the stress, homogenized
+values relative to their norm.  Newton and CG iteration counts must agree to
+within one (the paper's AD-vs-analytic identity of residuals and counts).
+"""
+
+import numpy as np
+import pytest
+
+from helpers import lame_fields, ncomp, pack, rel
+from oracle import closed_forms, materials, newton_cg
+from paper_2408_03804_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_FIELD = 1e-10
+TOL_HOMOG = 1e-11
+
+
+def make(shape, kin, mat, nphase=2, **kw):
+    from paper_2408_03804_amd.binding import FFTHomog
+    return FFTHomog(shape, kin, mat, nphase, **kw)
+
+
+def run_both(shape, kin, mat, phase, table, macro, n_inc, tol_cg=1e-12, tol_newton=1e-10, tangent=False,
+             k_mode=0, max_cg=20000):
+    d = len(shape)
+    h = make(shape, kin, mat, tol_cg=tol_cg, tol_newton=tol_newton, tangent=tangent, k_mode=k_mode, max_cg=max_cg)
+    h.set_material(phase, table)
+    S, psi, st = h.solve(macro, n_inc)
+    field = h.get_field(0).cpu().numpy()
+    stress = h.get_field(1).cpu().numpy()
+    lam, mu = lame_fields(phase, table)
+    prob = newton_cg.Problem(shape, mat, lam, mu)
+    ref = newton_cg.solve(prob, macro, n_increments=n_inc, tol_newton=tol_newton, tol_cg=tol_cg, max_cg=max_cg)
+    out = dict(h=h, S=S, psi=psi, st=st, prob=prob, ref=ref)
+    F_ref = ref["state"].field
+    F_gpu = np.moveaxis(field.reshape((d, d) + tuple(shape)), (0, 1), (-2, -1))
+    P_gpu = np.moveaxis(stress.reshape((d, d) + tuple(shape)), (0, 1), (-2, -1))
+    Fbar = ref["state"].macro
+    out["field_err"] = rel(F_gpu - Fbar, F_ref - Fbar)
+    out["stress_err"] = rel(P_gpu, prob.stress(F_ref))
+    return out
+
+
+def check_counts(gpu, ref):
+    assert ref["status"] == "ok" and gpu["status"] == "ok"
+    assert abs(gpu["newton"] - ref["newton"]) <= 1
+    if gpu["newton"] == ref["newton"]:
+        for a, b in zip(gpu["cg"], ref["cg"]):
+            assert abs(a - b) <= 1, (gpu["cg"], ref["cg"])
+
+
+def test_config1_disk_2d_linear_elastic():
+    """31 x 31 plane-strain disk inclusion, eps_xx = 0.01 (the small 2D workload), full parity."""
+    w = workloads.workload_disk2d(31)
+    o = run_both(w["shape"], "small", "linear_elastic", w["phase"], w["table"], w["macro"], 1, tangent=True)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
+    assert rel(o["S"], o["ref"]["macro_stress"]) < TOL_HOMOG
+    assert abs(o["psi"] - o["ref"]["energy"]) < TOL_HOMOG * abs(o["ref"]["energy"])
+    C, st = o["h"].tangent()
+    Cref, _, counts = newton_cg.homogenized_tangent(o["prob"], o["ref"]["state"], tol_cg=1e-12)
+    assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
+    for a, b in zip(st["cg"], counts):
+        assert abs(a - b) <= 1
+
+
+@pytest.mark.parametrize("shape", [(9, 10), (12, 7)])
+def test_neohookean_2d_increments(shape):
+    phase = workloads.random_phases(shape, 2, 3)
+    table = [[2.0, 1.0], [10.0, 5.0]]
+    F = np.array([[1.04, 0.02], [-0.01, 0.98]])
+    o = run_both(shape, "finite", "neo_hookean", phase, table, F.reshape(-1), 3)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
+    assert rel(o["S"], o["ref"]["macro_stress"]) < TOL_HOMOG
+
+
+@pytest.mark.parametrize("k_mode", [0, 1])
+def test_neohookean_3d_grf_increments(k_mode):
+    """The 3D finite-strain workload's generator at 16^3 (l = 4), F = diag(1.05,1,1) in 4 steps."""
+    w = workloads.workload_neohookean3d(n=16, correlation_length=4.0)
+    o = run_both(w["shape"], "finite", "neo_hookean", w["phase"], w["table"], w["macro"], 4, k_mode=k_mode)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
+    assert rel(o["S"], o["ref"]["macro_stress"]) < TOL_HOMOG
+    assert abs(o["psi"] - o["ref"]["energy"]) < TOL_HOMOG * abs(o["ref"]["energy"])
+
+
+def test_stvk_3d_ragged():
+    shape = (5, 7, 6)
+    phase = workloads.random_phases(shape, 2, 4)
+    table = [[1.0, 1.0], [3.0, 2.0]]
+    rng = np.random.default_rng(5)
+    F = np.eye(3) + 0.03 * rng.standard_normal((3, 3))
+    o = run_both(shape, "finite", "stvk", phase, table, F.reshape(-1), 2)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
+
+
+def test_spheres_3d_tangent_batched():
+    """RSA spheres (contrast 100) at 20^3: 6 x 6 tangent from 6 batched load cases."""
+    n = 20
+    phase = workloads.rsa_spheres(n, 6.0 * n / 64, 12.0 * n / 64, 0.2, 0)
+    table = np.array([workloads.lame(1.0, 0.3), workloads.lame(100.0, 0.3)])
+    macro = np.array([1e-2, 0, 0, 0, 0, 0.0])
+    o = run_both((n, n, n), "small", "linear_elastic", phase, table, macro, 1, tangent=True)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD
+    C, st = o["h"].tangent()
+    Cref, _, counts = newton_cg.homogenized_tangent(o["prob"], o["ref"]["state"], tol_cg=1e-12)
+    assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
+    assert np.abs(C - C.T).max() < 1e-12 * np.abs(C).max()
+    for a, b in zip(st["cg"], counts):
+        assert abs(a - b) <= 1
+
+
+def test_homogeneous_medium_zero_iterations_and_exact_tangent():
+    shape = (6, 5, 7)
+    h = make(shape, "small", "linear_elastic", tangent=True)
+    h.set_material(np.zeros(shape, np.uint8), [[1.3, 0.7], [1.3, 0.7]])
+    macro = np.array([1e-2, -2e-3, 3e-3, 1e-3, 0.0, 2e-3])
+    S, psi, st = h.solve(macro, 1)
+    assert st["cg_total"] == 0 and st["newton"] == 0
+    Cm = closed_forms.isotropic_matrix(1.3, 0.7, 3)
+    assert rel(S, Cm @ macro) < 1e-14
+    C, st = h.tangent()
+    assert st["cg_total"] == 0
+    assert np.abs(C - Cm).max() < 1e-14 * np.abs(Cm).max()
+
+
+def test_laminate_tangent_exact():
+    shape = (4, 6, 4)
+    phase = workloads.laminate(shape, 1, [0, 0, 1, 1, 1, 1])
+    table = [[1.0, 0.8], [6.0, 4.0]]
+    h = make(shape, "small", "linear_elastic", tangent=True, tol_cg=1e-14)
+    h.set_material(phase, table)
+    h.solve(np.zeros(6), 1)
+    C, _ = h.tangent()
+    ref = closed_forms.laminate([closed_forms.isotropic_tensor(*table[0], 3), closed_forms.isotropic_tensor(*table[1], 3)],
+                                [1 / 3, 2 / 3], [0.0, 1.0, 0.0])
+    assert np.abs(C - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_repeat_solve_is_bitwise_deterministic():
+    w = workloads.workload_neohookean3d(n=12, correlation_length=3.0)
+    outs = []
+    for _ in range(2):
+        h = make(w["shape"], "finite", "neo_hookean")
+        h.set_material(w["phase"], w["table"])
+        S, psi, st = h.solve(w["macro"], 2)
+        outs.append((S, psi, st["cg"], h.get_field(0).cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][3], outs[1][3])
+
+
+# ---- error paths (all forced from the host; every kernel exits normally) -----
+def test_cg_iteration_limit_reports_enotconv():
+    w = workloads.workload_disk2d(31)
+    h = make(w["shape"], "small", "linear_elastic", max_cg=1)
+    h.set_material(w["phase"], w["table"])
+    S, psi, st = h.solve(w["macro"], 1, allow=(2,))
+    assert st["status"] == "enotconv" and st["cg_total"] == 1
+
+
+def test_zero_load_needs_no_cg_and_negative_stiffness_breaks_down():
+    shape = (8, 8)
+    phase = workloads.random_phases(shape, 2, 1)
+    h = make(shape, "small", "linear_elastic")
+    h.set_material(phase, [[1.0, 1.0], [3.0, 2.0]])
+    S, psi, st = h.solve(np.zeros(3), 1)
+    assert st["status"] == "ok" and st["cg_total"] == 0 and np.all(S == 0.0)
+    h = make(shape, "small", "linear_elastic")
+    h.set_material(phase, [[-1.0, -1.0], [-3.0, -2.0]])
+    S, psi, st = h.solve(np.array([1e-2, 0, 0]), 1, allow=(4,))
+    assert st["status"] == "ebreakdown"
+
+
+def test_inverted_macro_reports_edomain():
+    shape = (6, 6)
+    h = make(shape, "finite", "neo_hookean")
+    h.set_material(np.zeros(shape, np.uint8), [[1.0, 1.0], [1.0, 1.0]])
+    S, psi, st = h.solve(np.array([-1.0, 0, 0, 1.0]), 1, allow=(3,))
+    assert st["status"] == "edomain"
+
+
+def test_tangent_before_solve_is_estate():
+    from paper_2408_03804_amd.binding import FFTHomogError
+    h = make((6, 6), "small", "linear_elastic", tangent=True)
+    with pytest.raises(FFTHomogError) as ei:
+        h.tangent()
+    assert ei.value.status == "estate"
+
+
+def test_bad_phase_id_rejected():
+    from paper_2408_03804_amd.binding import FFTHomogError
+    h = make((6, 6), "small", "linear_elastic")
+    ph = np.zeros((6, 6), np.uint8)
+    ph[2, 3] = 5
+    with pytest.raises(FFTHomogError) as ei:
+        h.set_material(ph, [[1.0, 1.0], [2.0, 2.0]])
+    assert ei.value.status == "einval"

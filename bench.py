@@ -34,13 +34,18 @@ def log(msg):
 
 
 def algorithmic_bytes_per_voxel(c, N, Nh, material_reads_strain=True):
-    """HBM bytes per voxel each CG-iteration kernel must move at minimum (FP64)."""
+    """HBM bytes per voxel each CG-iteration kernel must move at minimum (FP64).
+
+    xfwd reads r, p, x, the linearisation point F and the phase id and writes
+    p, x and the half spectrum; xinv reads the half spectrum and r and writes r;
+    the y and outer passes read and write the half spectrum once.
+    """
     f = 8.0 * c               # one packed field
-    s = 16.0 * c * Nh / N     # one half spectrum, per voxel
-    xfwd = 2 * f + (f if material_reads_strain else 0.0) + 1.0 + f + s   # r, p, F, phase in; p, spec out
+    s = 16.0 * c * Nh / N     # one half spectrum (nx/2+1 bins per row), per voxel
+    xfwd = 3 * f + (f if material_reads_strain else 0.0) + 1.0 + 2 * f + s
     mid = 2 * s
     outer = 2 * s
-    xinv = s + 3 * f + 2 * f                                            # spec, x, p, r in; x, r out
+    xinv = s + 2 * f
     return {"xfwd_cgop": xfwd, "reduce_pq": 0.0, "y_fwd": mid, "outer_project": outer, "y_inv": mid,
             "xinv_cgupdate": xinv, "reduce_rr": 0.0}
 
@@ -80,6 +85,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -92,6 +99,14 @@ def main():
     from paper_2408_03804_amd.binding import FFTHomog
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        return
     n = args.n
     w = workloads.workload_neohookean3d(n=n)
     shape = w["shape"]

@@ -28,19 +28,20 @@ struct Geom {
   int c;       // packed components per voxel
   int nx, ny, nz;
   int nxh;     // nx/2 + 1 half-spectrum bins along x
+  int nxp;     // row pitch of the stored half spectrum (nxh rounded up to 8 bins = 128 bytes)
   int n_outer, n_mid;
   long long N;   // voxels
-  long long Nh;  // half-spectrum bins per component
+  long long Nh;  // stored half-spectrum entries per component (nxp * ny * nz)
   double ks[3];  // 2 pi / L along x, y, z
   int small;     // small strain (Mandel packing) or finite strain
 };
 
-// Per-voxel Lame parameters: (lam, mu) = table[phase[v]] * density[v]^p.
+// Per-voxel Lame parameters: (lam, mu) = table[phase[v]] * scale[v], where
+// scale = density^p is precomputed once per set_material (nullable: 1).
 struct MatParams {
   const uint8_t* phase;
   const double* table;    // [nphase][2]
-  const double* density;  // nullable
-  double simp_p;
+  const double* scale;    // nullable
 };
 
 // CG bookkeeping of one right-hand side, kept on the device so alpha and beta

@@ -48,8 +48,9 @@ bool factorize(int n, int* radix, int* nst) {
 }
 
 struct Layout {
-  size_t F, x, r, p, spec, kst, phase, density, table, tw[3], partials, state, results, flags, total;
+  size_t F, x, r, p, spec, kst, phase, density, scale, table, tw[3], partials, state, results, flags, total;
   int B, R, TXm, TXo, nblk_x, nblk_vox;
+  int in_x, in_m, in_o;  // in-place (register-staged) FFT per pass
   size_t n_partials, smem_max;
 };
 
@@ -60,10 +61,11 @@ bool make_geom(const fft_homog_desc* d, Geom* g) {
   g->ny = d->n[1];
   g->nz = d->ndim == 3 ? d->n[2] : 1;
   g->nxh = g->nx / 2 + 1;
+  g->nxp = g->nxh >= 8 ? (g->nxh + 7) / 8 * 8 : g->nxh;
   g->n_outer = d->ndim == 3 ? g->nz : g->ny;
   g->n_mid = d->ndim == 3 ? g->ny : 1;
   g->N = (long long)g->nx * g->ny * g->nz;
-  g->Nh = (long long)g->nxh * g->ny * g->nz;
+  g->Nh = (long long)g->nxp * g->ny * g->nz;
   const double twopi = 6.283185307179586476925286766559;
   for (int a = 0; a < 3; ++a) g->ks[a] = (a < d->ndim) ? twopi / d->len[a] : 0.0;
   g->small = d->kinematics == FFT_HOMOG_SMALL_STRAIN;
@@ -101,36 +103,60 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
     if (!factorize(d->n[a], rad, &ns)) return FFT_HOMOG_EUNSUPPORTED;
   }
   L->B = (d->flags & FFT_HOMOG_FLAG_TANGENT) ? C : 1;
+  AxisPlan pl[3];
+  for (int a = 0; a < 3; ++a) {
+    pl[a].n = a < d->ndim ? d->n[a] : 1;
+    factorize(pl[a].n, pl[a].radix, &pl[a].nstages);
+    pl[a].tw = nullptr;
+  }
+  const AxisPlan& pouter = pl[d->ndim - 1];
   const int rows = g.ny * g.nz;
-  // x pass: rows per block
-  int R = 0;
-  for (int r = 16; r >= 1; --r) {
+  // x pass: rows per block, aiming at one or two voxels per thread
+  int rmax = std::max(1, std::min(16, (2 * kThreads + g.nx - 1) / g.nx));
+  int R = 0, inx = 0;
+  for (int r = rmax; r >= 1; --r) {
     if (r > rows && r > 1) continue;
-    if (xfwd_smem(g, r) <= kLdsFft && xinv_smem(g, r) <= kLdsFft) { R = r; break; }
+    const int P = (C * r + 1) / 2;
+    const int ip = inplace_ok(pl[0], P) ? 1 : 0;
+    if (xfwd_smem(g, r, ip) <= kLdsFft && xinv_smem(g, r, ip) <= kLdsFft) { R = r; inx = ip; break; }
   }
   if (R == 0) {
-    if (xfwd_smem(g, 1) <= kLdsMax && xinv_smem(g, 1) <= kLdsMax) R = 1;
+    const int P = (C + 1) / 2;
+    inx = inplace_ok(pl[0], P) ? 1 : 0;
+    if (xfwd_smem(g, 1, inx) <= kLdsMax && xinv_smem(g, 1, inx) <= kLdsMax) R = 1;
     else return FFT_HOMOG_EUNSUPPORTED;
   }
   L->R = R;
-  int TXm = 1;
+  L->in_x = inx;
+  int TXm = 0, inm = 0;
   for (int t = 16; t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
-    if (mid_smem(g, t) <= kLdsFft) { TXm = t; break; }
+    const int ip = inplace_ok(pl[1], t) ? 1 : 0;
+    if (mid_smem(g, t, ip) <= kLdsFft) { TXm = t; inm = ip; break; }
   }
-  if (mid_smem(g, TXm) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
+  if (TXm == 0) {
+    TXm = 1;
+    inm = inplace_ok(pl[1], 1) ? 1 : 0;
+    if (mid_smem(g, 1, inm) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
+  }
   L->TXm = TXm;
-  int TXo = 0;
+  L->in_m = inm;
+  const int G = outer_group(g);
+  int TXo = 0, ino = 0;
   for (int t = 16; t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
-    if (outer_smem(g, t) <= kLdsOuter) { TXo = t; break; }
+    const int ip = inplace_ok(pouter, G * t) ? 1 : 0;
+    if (outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }
   }
   if (TXo == 0) {
-    if (outer_smem(g, 1) <= kLdsMax) TXo = 1;
-    else return FFT_HOMOG_EUNSUPPORTED;
+    TXo = 1;
+    ino = inplace_ok(pouter, G) ? 1 : 0;
+    if (outer_smem(g, 1, ino) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
   }
   L->TXo = TXo;
-  L->smem_max = std::max(std::max(xfwd_smem(g, R), xinv_smem(g, R)), std::max(mid_smem(g, TXm), outer_smem(g, TXo)));
+  L->in_o = ino;
+  L->smem_max = std::max(std::max(xfwd_smem(g, R, inx), xinv_smem(g, R, inx)),
+                         std::max(mid_smem(g, TXm, inm), outer_smem(g, TXo, ino)));
   L->nblk_x = (rows + R - 1) / R;
   L->nblk_vox = (int)((g.N + kThreads - 1) / kThreads);
 
@@ -149,6 +175,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->kst = take(d->k_mode == FFT_HOMOG_K_STORED ? (size_t)C * (C + 1) / 2 * g.N * sizeof(double) : 0);
   L->phase = take((size_t)g.N);
   L->density = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
+  L->scale = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
   L->table = take(2 * kMaxPhase * sizeof(double));
   for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? (size_t)d->n[a] * sizeof(double2) : 0);
   size_t np = (size_t)L->B * L->nblk_x;
@@ -172,7 +199,8 @@ struct fft_homog {
   int matcode;
   hipStream_t stream;
   char* ws;
-  double *F, *x, *r, *p, *kst, *partials, *results, *table, *density;
+  double *F, *x, *r, *p, *kst, *partials, *results, *table, *density, *scale;
+  double simp_p;
   double2* spec;
   uint8_t* phase;
   int* flags;
@@ -209,6 +237,8 @@ XFwdArgs xfwd_args(fft_homog_t* h) {
   a.px = h->plan[0];
   a.R = h->L.R;
   a.nblocks = h->L.nblk_x;
+  a.inplace = h->L.in_x;
+  a.x = h->x;
   a.F = h->F;
   a.Kst = h->kst;
   a.spec = h->spec;
@@ -225,10 +255,10 @@ XInvArgs xinv_args(fft_homog_t* h) {
   a.px = h->plan[0];
   a.R = h->L.R;
   a.nblocks = h->L.nblk_x;
+  a.inplace = h->L.in_x;
   a.spec = h->spec;
   a.x = h->x;
   a.r = h->r;
-  a.p = h->p;
   a.st = h->st;
   a.partials = h->partials;
   a.scale = 1.0 / (double)h->g.N;
@@ -240,6 +270,7 @@ AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st) {
   a.g = h->g;
   a.pl = h->plan[axis];
   a.TX = TX;
+  a.inplace = (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
   a.spec = h->spec;
   a.st = st;
   return a;
@@ -314,6 +345,12 @@ int cg_loop(fft_homog_t* h, int B) {
     }
     int rc = read_states(h, B);
     if (rc) return rc;
+    bool still = false;
+    for (int b = 0; b < B; ++b) still = still || h->h_st[b].status == CG_RUNNING;
+    if (!still) {
+      FH_CK(launch_cg_finish(h->x, h->p, h->st, h->g, B, h->stream));
+      return FFT_HOMOG_OK;
+    }
   }
 }
 
@@ -385,6 +422,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   h->kst = d->k_mode == FFT_HOMOG_K_STORED ? (double*)(h->ws + L.kst) : nullptr;
   h->phase = (uint8_t*)(h->ws + L.phase);
   h->density = (d->flags & FFT_HOMOG_FLAG_DENSITY) ? (double*)(h->ws + L.density) : nullptr;
+  h->scale = (d->flags & FFT_HOMOG_FLAG_DENSITY) ? (double*)(h->ws + L.scale) : nullptr;
   h->table = (double*)(h->ws + L.table);
   h->partials = (double*)(h->ws + L.partials);
   h->st = (CgState*)(h->ws + L.state);
@@ -440,8 +478,8 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   }
   h->mat.phase = h->phase;
   h->mat.table = h->table;
-  h->mat.density = nullptr;
-  h->mat.simp_p = 0.0;
+  h->mat.scale = nullptr;
+  h->simp_p = 0.0;
   *out = h;
   return FFT_HOMOG_OK;
 }
@@ -454,9 +492,12 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
     if (!std::isfinite(lm[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite phase table entry");
   FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)h->g.N, hipMemcpyDeviceToDevice, h->stream));
   FH_CK(hipMemcpyAsync(h->table, lm, 2 * h->desc.nphase * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  if (density) FH_CK(hipMemcpyAsync(h->density, density, (size_t)h->g.N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  h->mat.density = density ? h->density : nullptr;
-  h->mat.simp_p = simp_p;
+  if (density) {
+    FH_CK(hipMemcpyAsync(h->density, density, (size_t)h->g.N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    FH_CK(launch_simp_scale(h->density, simp_p, h->scale, h->g.N, h->stream));
+  }
+  h->mat.scale = density ? h->scale : nullptr;
+  h->simp_p = simp_p;
   h->h_flags[0] = 0;
   FH_CK(hipMemcpyAsync(h->flags, h->h_flags, sizeof(int), hipMemcpyHostToDevice, h->stream));
   FH_CK(launch_check_phase(h->phase, h->g.N, h->desc.nphase, h->flags, h->stream));
@@ -671,8 +712,9 @@ int fft_homog_debug_rfft(fft_homog_t* h, const double* in, double* spec, int bat
   FH_CK(launch_xfwd(PROD_IDENT, h->matcode, a, batch, h->stream));
   rc = spectral_middle(h, OUTER_FWD, batch, nullptr);
   if (rc) return rc;
-  FH_CK(hipMemcpyAsync(spec, h->spec, (size_t)batch * h->g.c * h->g.Nh * sizeof(double2), hipMemcpyDeviceToDevice,
-                       h->stream));
+  FH_CK(hipMemcpy2DAsync(spec, h->g.nxh * sizeof(double2), h->spec, h->g.nxp * sizeof(double2),
+                         h->g.nxh * sizeof(double2), (size_t)batch * h->g.c * h->g.ny * h->g.nz,
+                         hipMemcpyDeviceToDevice, h->stream));
   FH_CK(hipStreamSynchronize(h->stream));
   return FFT_HOMOG_OK;
 }
@@ -681,8 +723,9 @@ int fft_homog_debug_irfft(fft_homog_t* h, const double* spec, double* out, int b
   if (!h || !spec || !out) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   int rc = check_batch(h, batch);
   if (rc) return rc;
-  FH_CK(hipMemcpyAsync(h->spec, spec, (size_t)batch * h->g.c * h->g.Nh * sizeof(double2), hipMemcpyDeviceToDevice,
-                       h->stream));
+  FH_CK(hipMemcpy2DAsync(h->spec, h->g.nxp * sizeof(double2), spec, h->g.nxh * sizeof(double2),
+                         h->g.nxh * sizeof(double2), (size_t)batch * h->g.c * h->g.ny * h->g.nz,
+                         hipMemcpyDeviceToDevice, h->stream));
   rc = spectral_middle(h, OUTER_INV, batch, nullptr);
   if (rc) return rc;
   XInvArgs a = xinv_args(h);

@@ -198,6 +198,85 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
   return src;
 }
 
+// ---- in-place variant: register-staged stages, one LDS buffer ---------------
+// Every stage first loads all butterfly inputs of the thread into registers,
+// synchronises, then writes the outputs to their Stockham positions in the same
+// buffer.  Usable when all radices are 2/3/4/5/8 and no thread owns more than
+// kInplaceElems elements in a stage (checked by the host: inplace_ok()).
+constexpr int kInplaceElems = 16;
+
+template <int R, int DIR>
+__device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nseq, int n, int Ns,
+                                              const double2* __restrict__ tw) {
+  constexpr int MB = kInplaceElems / R;
+  const int nb = n / R;
+  const int stride = n / (Ns * R);
+  const int total = nb * nseq;
+  double2 v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    if (w < total) {
+      const int j = w / nseq;
+      const int s = w - j * nseq;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[i][t] = buf[(j + t * nb) * nseq + s];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    if (w < total) {
+      const int j = w / nseq;
+      const int s = w - j * nseq;
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * stride));
+      }
+      dft_small<R, DIR>(v[i]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[(base + t * Ns) * nseq + s] = v[i][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIR>
+__device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
+  const int n = pl.n;
+  int Ns = 1;
+  for (int st = 0; st < pl.nstages; ++st) {
+    const int R = pl.radix[st];
+    switch (R) {
+      case 2: stage_inplace<2, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      case 3: stage_inplace<3, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      case 4: stage_inplace<4, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      case 5: stage_inplace<5, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      default: stage_inplace<8, DIR>(buf, nseq, n, Ns, pl.tw); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Transform in place when the plan allows it (inplace != 0), else ping-pong
+// through `pong` and copy back.  Result always in `buf`.
+template <int DIR>
+__device__ __forceinline__ void fft_lds_any(double2* buf, double2* pong, int nseq, const AxisPlan& pl, int inplace) {
+  if (inplace) {
+    fft_lds_inplace<DIR>(buf, nseq, pl);
+  } else {
+    double2* res = fft_lds<DIR>(buf, pong, nseq, pl);
+    if (res != buf) {
+      const int cnt = pl.n * nseq;
+      for (int t = threadIdx.x; t < cnt; t += blockDim.x) buf[t] = res[t];
+      __syncthreads();
+    }
+  }
+}
+
 // ---- deterministic block reduction (wave64 shuffles, fixed order) ------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

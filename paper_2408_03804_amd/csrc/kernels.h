@@ -16,8 +16,10 @@ struct XFwdArgs {
   AxisPlan px;
   int R;                 // rows (y,z lines) per block
   int nblocks;           // blocks per right-hand side
+  int inplace;           // FFT stages staged through registers (one LDS buffer)
   const double* in;      // IDENT: field [B][c][N]; CGOP: residual r [B][c][N]
   double* p;             // CGOP: search direction, updated in place
+  double* x;             // CGOP: CG solution, receives the previous iteration's alpha p
   const double* F;       // linearisation point / strain [c][N]
   const double* Kst;     // stored tangent [c(c+1)/2][N]
   double2* spec;         // [B][c][Nh]
@@ -33,11 +35,11 @@ struct XInvArgs {
   AxisPlan px;
   int R;
   int nblocks;
+  int inplace;
   const double2* spec;
   double* out;           // IDENT output [B][c][N]
-  double* x;             // CG solution [B][c][N]
+  double* x;             // RHS: CG solution [B][c][N], set to zero
   double* r;             // CG residual [B][c][N]
-  const double* p;       // CG direction [B][c][N]
   CgState* st;
   double* partials;
   double scale;          // 1 / N
@@ -48,20 +50,27 @@ struct AxisArgs {
   Geom g;
   AxisPlan pl;
   int TX;                // kx bins per block
+  int inplace;
   double2* spec;
   const CgState* st;     // nullable: skip right-hand sides whose CG is not running
 };
 
-size_t xfwd_smem(const Geom& g, int R);
-size_t xinv_smem(const Geom& g, int R);
-size_t mid_smem(const Geom& g, int TX);
-size_t outer_smem(const Geom& g, int TX);
+// dynamic LDS bytes of each pass; `inplace` drops the ping-pong buffer
+size_t xfwd_smem(const Geom& g, int R, int inplace);
+size_t xinv_smem(const Geom& g, int R, int inplace);
+size_t mid_smem(const Geom& g, int TX, int inplace);
+size_t outer_smem(const Geom& g, int TX, int inplace);
+int outer_group(const Geom& g);   // components transformed together in the outer pass
+// true if an in-place transform of nseq sequences of this plan fits the register staging
+bool inplace_ok(const AxisPlan& pl, int nseq);
 
 hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s);
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s);
 hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s);
 hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s);
+// x += alpha p for every right-hand side whose CG stopped after at least one full iteration
+hipError_t launch_cg_finish(double* x, const double* p, const CgState* st, const Geom& g, int B, hipStream_t s);
 
 // Newton-level and post-processing kernels.
 hipError_t launch_init_reference(double* F, const Geom& g, hipStream_t s);
@@ -79,6 +88,7 @@ hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipS
 hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s);
 hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* full_out, double* energy_out,
                                const Geom& g, hipStream_t s);
+hipError_t launch_simp_scale(const double* density, double p, double* scale, long long N, hipStream_t s);
 hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s);
 hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE,
                                      double* psi, MatParams m, const Geom& g, hipStream_t s);

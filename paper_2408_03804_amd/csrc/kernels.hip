@@ -3,20 +3,20 @@
 // One CG iteration (section 3 equilibrium operator, section 3.2 incremental
 // stress, Appendix A linear solve) is five passes over the data:
 //
-//   xfwd   per voxel: p = r + beta p, tau = K(F) : p by dual numbers, partial
-//          <p, tau>; real-to-complex FFT of tau along x (rows in LDS)
+//   xfwd   per voxel: x += alpha_prev p, p = r + beta p, tau = K(F) : p by dual
+//          numbers, partial <p, tau>; real-to-complex FFT of tau along x
 //   mid    complex FFT along y of the half spectrum            (3D only)
-//   outer  FFT along the outer axis, G-hat(xi) : tau-hat for all components of
-//          each wavevector, inverse FFT along the outer axis
+//   outer  FFT along the outer axis, G-hat(xi) : tau-hat on each wavevector,
+//          inverse FFT along the outer axis
 //   mid    inverse FFT along y                                 (3D only)
-//   xinv   complex-to-real FFT along x, then x += alpha p, r -= alpha q and a
-//          partial <r, r>
+//   xinv   complex-to-real FFT along x, r -= alpha q, partial <r, r>
 //
 // plus two one-block reductions that turn the partial sums into alpha and beta
 // on the device.  <p, q> is taken as <p, K:p>: p lies in the range of the
 // projection G (it is built from projected residuals) and G is self-adjoint, so
-// <p, G(K:p)> = <G p, K:p> = <p, K:p> in exact arithmetic, and the xinv pass
-// then needs neither q in memory nor a re-read of p for the dot product.
+// <p, G(K:p)> = <G p, K:p> = <p, K:p> in exact arithmetic; q is therefore never
+// stored.  The update x += alpha p of iteration k is applied by the xfwd pass of
+// iteration k+1, which reads p anyway (k_cg_finish applies the last one).
 #include "common.h"
 #include "fft_lds.h"
 #include "kernels.h"
@@ -40,8 +40,8 @@ __device__ __forceinline__ void load_lame(const MatParams& m, long long v, doubl
   const int ph = m.phase[v];
   lam = m.table[2 * ph];
   mu = m.table[2 * ph + 1];
-  if (m.density != nullptr) {
-    const double s = pow(m.density[v], m.simp_p);
+  if (m.scale != nullptr) {
+    const double s = m.scale[v];
     lam *= s;
     mu *= s;
   }
@@ -55,8 +55,9 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 template <int PROD, int MAT, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
+  constexpr bool CGOP = (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED);
   const int b = blockIdx.y;
-  if (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED) {
+  if (CGOP) {
     if (a.st[b].status != CG_RUNNING) return;
   }
   const Geom& g = a.g;
@@ -68,19 +69,52 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   const int P = (nseq + 1) >> 1;
   extern __shared__ double2 smem[];
   double2* A = smem;
-  double2* Bf = smem + (size_t)nx * P;
+  double2* Bf = smem + (size_t)nx * P;  // ping-pong partner (unused in place)
   __shared__ double red[kThreads / 64];
 
-  double beta = 0.0;
+  double beta = 0.0, alpha_prev = 0.0;
   int first = 1;
-  if (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED) {
+  if (CGOP) {
     beta = a.st[b].beta;
+    alpha_prev = a.st[b].alpha;
     first = a.st[b].first;
   }
   const long long N = g.N;
   double acc = 0.0;
   int bad = 0;
 
+  // LDS slot of component j of row r at column x (two real rows per complex sequence)
+  auto slot = [&](int j, int r, int x) -> double* {
+    const int qr = j * nr + r;
+    return reinterpret_cast<double*>(&A[x * P + (qr >> 1)]) + (qr & 1);
+  };
+
+  if (CGOP) {
+    // phase A: CG vectors.  x += alpha_prev p_old ; p = r + beta p_old, staged in LDS
+    for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
+      const int r = t / nx;
+      const int x = t - r * nx;
+      const long long vox = (long long)(row0 + r) * nx + x;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const long long idx = ((long long)b * C + j) * N + vox;
+        const double rj = a.in[idx];
+        double pj;
+        if (first) {
+          pj = rj;
+        } else {
+          const double po = a.p[idx];
+          a.x[idx] += alpha_prev * po;
+          pj = rj + beta * po;
+        }
+        a.p[idx] = pj;
+        *slot(j, r, x) = pj;
+      }
+    }
+  }
+
+  // phase B (or the only phase): per-voxel producer, result into the LDS slots
+#pragma unroll 1
   for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
     const int r = t / nx;
     const int x = t - r * nx;
@@ -95,7 +129,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       double e[C];
       // the linear elastic energy is quadratic: K does not depend on the strain,
       // so the tangent passes do not read it
-      const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE);
+      const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE && PROD != PROD_CGOP_STORED);
 #pragma unroll
       for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
       if (PROD == PROD_STRESS) {
@@ -116,15 +150,10 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) acc += v[j] * v[j];
-      } else {  // CG operator
+      } else {  // CG operator: v = K : p with p from phase A
         double pv[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-          const long long idx = ((long long)b * C + j) * N + vox;
-          const double rj = a.in[idx];
-          pv[j] = first ? rj : rj + beta * a.p[idx];
-          a.p[idx] = pv[j];
-        }
+        for (int j = 0; j < C; ++j) pv[j] = *slot(j, r, x);
         if (PROD == PROD_CGOP) {
           tangent_jvp_ad<MAT, NDIM>(e, pv, lam, mu, v);
         } else {
@@ -148,11 +177,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       }
     }
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int qr = j * nr + r;
-      double* d = reinterpret_cast<double*>(&A[x * P + (qr >> 1)]);
-      d[qr & 1] = v[j];
-    }
+    for (int j = 0; j < C; ++j) *slot(j, r, x) = v[j];
   }
   if (nseq & 1) {
     for (int x = threadIdx.x; x < nx; x += blockDim.x) A[x * P + P - 1].y = 0.0;
@@ -160,7 +185,8 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   if (PROD == PROD_STRESS && bad) a.st[b].domain = 1;
   __syncthreads();
 
-  const double2* res = fft_lds<-1>(A, Bf, P, a.px);
+  fft_lds_any<-1>(A, Bf, P, a.px, a.inplace);
+  const double2* res = A;
 
   // separate the two real rows packed in each complex sequence
   const int nxh = g.nxh;
@@ -172,12 +198,12 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
     const int qa = 2 * q;
     const int ja = qa / nr;
     const int ra = qa - ja * nr;
-    a.spec[((long long)b * C + ja) * g.Nh + (long long)(row0 + ra) * nxh + k] =
+    a.spec[((long long)b * C + ja) * g.Nh + (long long)(row0 + ra) * g.nxp + k] =
         make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
     if (qa + 1 < nseq) {
       const int jb = (qa + 1) / nr;
       const int rb = (qa + 1) - jb * nr;
-      a.spec[((long long)b * C + jb) * g.Nh + (long long)(row0 + rb) * nxh + k] =
+      a.spec[((long long)b * C + jb) * g.Nh + (long long)(row0 + rb) * g.nxp + k] =
           make_double2(0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x));
     }
   }
@@ -207,8 +233,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
   const int P = (nseq + 1) >> 1;
   extern __shared__ double2 smem[];
   double2* A = smem;
-  double2* Bf = smem + (size_t)nx * P;  // also holds the loaded half rows
-  double2* H = Bf;
+  double2* H = smem + (size_t)nx * P;  // loaded half rows, then the ping-pong partner
   __shared__ double red[kThreads / 64];
 
   for (int t = threadIdx.x; t < nseq * nxh; t += blockDim.x) {
@@ -216,7 +241,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
     const int k = t - qr * nxh;
     const int j = qr / nr;
     const int r = qr - j * nr;
-    H[k * nseq + qr] = a.spec[((long long)b * C + j) * g.Nh + (long long)(row0 + r) * nxh + k];
+    H[k * nseq + qr] = a.spec[((long long)b * C + j) * g.Nh + (long long)(row0 + r) * g.nxp + k];
   }
   __syncthreads();
   for (int t = threadIdx.x; t < P * nx; t += blockDim.x) {
@@ -243,7 +268,8 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
   }
   __syncthreads();
 
-  const double2* res = fft_lds<+1>(A, Bf, P, a.px);
+  fft_lds_any<+1>(A, H, P, a.px, a.inplace);
+  const double2* res = A;
 
   const long long N = g.N;
   double alpha = 0.0;
@@ -266,8 +292,6 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
         a.x[idx] = 0.0;
         acc += u * u;
       } else {
-        const double pj = a.p[idx];
-        a.x[idx] += alpha * pj;
         const double rn = a.r[idx] - alpha * u;
         a.r[idx] = rn;
         acc += rn * rn;
@@ -278,6 +302,19 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[(long long)b * a.nblocks + blockIdx.x] = s;
   }
+}
+
+// x += alpha p after the last CG iteration of each right-hand side (the
+// iteration-k update is otherwise folded into the next x-forward pass)
+__global__ void __launch_bounds__(kThreads) k_cg_finish(double* x, const double* p, const CgState* st, Geom g) {
+  const int b = blockIdx.y;
+  const CgState& S = st[b];
+  if (S.iters < 1 || (S.status != CG_CONVERGED && S.status != CG_MAXIT)) return;
+  const double alpha = S.alpha;
+  const long long tot = (long long)g.c * g.N;
+  const long long off = (long long)b * tot;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x)
+    x[off + i] += alpha * p[off + i];
 }
 
 // ============================================================================
@@ -294,18 +331,18 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   extern __shared__ double2 smem[];
   double2* A = smem;
   double2* Bf = smem + (size_t)ny * tw;
-  const long long base = (long long)blockIdx.z * g.Nh + (long long)blockIdx.y * ny * g.nxh + kx0;
+  const long long base = (long long)blockIdx.z * g.Nh + (long long)blockIdx.y * ny * g.nxp + kx0;
   for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
     const int y = t / tw;
     const int s = t - y * tw;
-    A[t] = a.spec[base + (long long)y * g.nxh + s];
+    A[t] = a.spec[base + (long long)y * g.nxp + s];
   }
   __syncthreads();
-  const double2* res = fft_lds<DIR>(A, Bf, tw, a.pl);
+  fft_lds_any<DIR>(A, Bf, tw, a.pl, a.inplace);
   for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
     const int y = t / tw;
     const int s = t - y * tw;
-    a.spec[base + (long long)y * g.nxh + s] = res[t];
+    a.spec[base + (long long)y * g.nxp + s] = A[t];
   }
 }
 
@@ -385,45 +422,45 @@ __device__ __forceinline__ void project_small(double2* v, const double* nv) {
   }
 }
 
+// Finite strain projects each row of F on its own ((A n)_i n_j involves only
+// row i), so a block transforms the NDIM components of one row; small strain
+// couples all C Mandel components.  LDS layout: element o of sequence (jj, s)
+// at D[o * nseq + jj * tw + s], nseq = G * tw, one FFT call for all of them.
 template <int MODE, int SMALL, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
   constexpr int C = SMALL ? (NDIM == 3 ? 6 : 3) : (NDIM == 3 ? 9 : 4);
+  constexpr int G = SMALL ? C : NDIM;
+  constexpr int NGRP = C / G;
   const Geom& g = a.g;
-  const int b = blockIdx.z;
+  const int b = blockIdx.z / NGRP;
+  const int grp = blockIdx.z - b * NGRP;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
   const int kx0 = blockIdx.x * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
   const int mid = blockIdx.y;
   const int n = g.n_outer;
-  const int cnt = n * tw;
+  const int nseq = G * tw;
+  const int cnt = n * nseq;
   extern __shared__ double2 smem[];
   double2* D = smem;
-  double2* pong = smem + (size_t)C * cnt;
-  const long long ostride = (long long)g.n_mid * g.nxh;
-  const long long base0 = (long long)mid * g.nxh + kx0;
+  double2* pong = smem + (size_t)cnt;
+  const long long ostride = (long long)g.n_mid * g.nxp;
+  const long long base0 = (long long)mid * g.nxp + kx0;
+  const long long cbase = ((long long)b * C + grp * G) * g.Nh;
 
-  for (int t = threadIdx.x; t < C * cnt; t += blockDim.x) {
-    const int j = t / cnt;
-    const int rem = t - j * cnt;
-    const int o = rem / tw;
-    const int s = rem - o * tw;
-    D[t] = a.spec[((long long)b * C + j) * g.Nh + base0 + o * ostride + s];
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int o = t / nseq;
+    const int rem = t - o * nseq;
+    const int jj = rem / tw;
+    const int s = rem - jj * tw;
+    D[t] = a.spec[cbase + (long long)jj * g.Nh + base0 + o * ostride + s];
   }
   __syncthreads();
 
-  if (MODE != OUTER_INV) {
-    for (int j = 0; j < C; ++j) {
-      double2* Dj = D + (size_t)j * cnt;
-      const double2* res = fft_lds<-1>(Dj, pong, tw, a.pl);
-      if (res != Dj) {
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) Dj[t] = res[t];
-        __syncthreads();
-      }
-    }
-  }
+  if (MODE != OUTER_INV) fft_lds_any<-1>(D, pong, nseq, a.pl, a.inplace);
 
   if (MODE == OUTER_PROJECT) {
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    for (int t = threadIdx.x; t < n * tw; t += blockDim.x) {
       const int o = t / tw;
       const int s = t - o * tw;
       double xi[NDIM];
@@ -437,43 +474,46 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
       double nrm2 = 0.0;
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) nrm2 += xi[i] * xi[i];
-      double2 v[C];
+      double2 v[G];
+      const int e0 = o * nseq + s;
       if (nrm2 > 0.0) {
         const double inv = 1.0 / sqrt(nrm2);
         double nv[NDIM];
 #pragma unroll
         for (int i = 0; i < NDIM; ++i) nv[i] = xi[i] * inv;
 #pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = D[(size_t)j * cnt + t];
-        if (SMALL) project_small<NDIM>(v, nv);
-        else project_finite<NDIM>(v, nv);
+        for (int jj = 0; jj < G; ++jj) v[jj] = D[e0 + jj * tw];
+        if (SMALL) {
+          project_small<NDIM>(v, nv);
+        } else {
+          // one row of F: (sum_j A_j n_j) n
+          double2 an = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int jj = 0; jj < G; ++jj) {
+            an.x += v[jj].x * nv[jj];
+            an.y += v[jj].y * nv[jj];
+          }
+#pragma unroll
+          for (int jj = 0; jj < G; ++jj) v[jj] = make_double2(an.x * nv[jj], an.y * nv[jj]);
+        }
       } else {
 #pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = make_double2(0.0, 0.0);
+        for (int jj = 0; jj < G; ++jj) v[jj] = make_double2(0.0, 0.0);
       }
 #pragma unroll
-      for (int j = 0; j < C; ++j) D[(size_t)j * cnt + t] = v[j];
+      for (int jj = 0; jj < G; ++jj) D[e0 + jj * tw] = v[jj];
     }
     __syncthreads();
   }
 
-  if (MODE != OUTER_FWD) {
-    for (int j = 0; j < C; ++j) {
-      double2* Dj = D + (size_t)j * cnt;
-      const double2* res = fft_lds<+1>(Dj, pong, tw, a.pl);
-      if (res != Dj) {
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) Dj[t] = res[t];
-        __syncthreads();
-      }
-    }
-  }
+  if (MODE != OUTER_FWD) fft_lds_any<+1>(D, pong, nseq, a.pl, a.inplace);
 
-  for (int t = threadIdx.x; t < C * cnt; t += blockDim.x) {
-    const int j = t / cnt;
-    const int rem = t - j * cnt;
-    const int o = rem / tw;
-    const int s = rem - o * tw;
-    a.spec[((long long)b * C + j) * g.Nh + base0 + o * ostride + s] = D[t];
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int o = t / nseq;
+    const int rem = t - o * nseq;
+    const int jj = rem / tw;
+    const int s = rem - jj * tw;
+    a.spec[cbase + (long long)jj * g.Nh + base0 + o * ostride + s] = D[t];
   }
 }
 
@@ -726,6 +766,12 @@ __global__ void __launch_bounds__(kThreads) k_stress_field(const double* F, MatP
   if (energy_out != nullptr) energy_out[v] = psi;
 }
 
+// scale[v] = density[v]^p (SIMP interpolation of the Lame parameters)
+__global__ void k_simp_scale(const double* density, double p, double* scale, long long N) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x)
+    scale[v] = pow(density[v], p);
+}
+
 __global__ void k_check_phase(const uint8_t* phase, long long N, int nphase, int* flag) {
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x)
     if (phase[v] >= nphase) flag[0] = 1;
@@ -757,26 +803,39 @@ __global__ void __launch_bounds__(kThreads) k_debug_constitutive(const double* e
 // ============================================================================
 // host launchers
 // ============================================================================
-size_t xfwd_smem(const Geom& g, int R) {
+size_t xfwd_smem(const Geom& g, int R, int inplace) {
   const int P = (g.c * R + 1) / 2;
-  return 2ull * g.nx * P * sizeof(double2);
+  return (inplace ? 1ull : 2ull) * g.nx * P * sizeof(double2);
 }
-size_t xinv_smem(const Geom& g, int R) {
+size_t xinv_smem(const Geom& g, int R, int inplace) {
   const int P = (g.c * R + 1) / 2;
   const size_t a = (size_t)g.nx * P;
-  size_t bsz = (size_t)g.nx * P;
+  size_t bsz = inplace ? 0 : (size_t)g.nx * P;
   const size_t h = (size_t)g.nxh * g.c * R;
   if (h > bsz) bsz = h;
   return (a + bsz) * sizeof(double2);
 }
-size_t mid_smem(const Geom& g, int TX) { return 2ull * g.ny * TX * sizeof(double2); }
-size_t outer_smem(const Geom& g, int TX) { return (size_t)(g.c + 1) * g.n_outer * TX * sizeof(double2); }
+size_t mid_smem(const Geom& g, int TX, int inplace) { return (inplace ? 1ull : 2ull) * g.ny * TX * sizeof(double2); }
+int outer_group(const Geom& g) { return g.small ? g.c : g.ndim; }
+size_t outer_smem(const Geom& g, int TX, int inplace) {
+  return (size_t)(outer_group(g) * (inplace ? 1 : 2)) * g.n_outer * TX * sizeof(double2);
+}
+bool inplace_ok(const AxisPlan& pl, int nseq) {
+  for (int st = 0; st < pl.nstages; ++st) {
+    const int R = pl.radix[st];
+    if (R != 2 && R != 3 && R != 4 && R != 5 && R != 8) return false;
+    const long long total = (long long)nseq * (pl.n / R);
+    const long long per_thread = (total + kThreads - 1) / kThreads;
+    if (per_thread > kInplaceElems / R) return false;
+  }
+  return true;
+}
 
 static inline int nblk_rows(const Geom& g, int R) { return (g.ny * g.nz + R - 1) / R; }
 
 hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s) {
   dim3 grid(nblk_rows(a.g, a.R), B);
-  const size_t sm = xfwd_smem(a.g, a.R);
+  const size_t sm = xfwd_smem(a.g, a.R, a.inplace);
 #define FH_L(M, D)                                                                                       \
   switch (prod) {                                                                                        \
     case PROD_IDENT: hipLaunchKernelGGL((k_xfwd<PROD_IDENT, M, D>), grid, dim3(kThreads), sm, s, a); break;   \
@@ -794,7 +853,7 @@ hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t 
 
 hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
   dim3 grid(nblk_rows(a.g, a.R), B);
-  const size_t sm = xinv_smem(a.g, a.R);
+  const size_t sm = xinv_smem(a.g, a.R, a.inplace);
 #define FH_L(CC)                                                                                        \
   switch (cons) {                                                                                       \
     case CONS_IDENT: hipLaunchKernelGGL((k_xinv<CONS_IDENT, CC>), grid, dim3(kThreads), sm, s, a); break; \
@@ -815,15 +874,15 @@ hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
 
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
   dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.nz, B * a.g.c);
-  const size_t sm = mid_smem(a.g, a.TX);
+  const size_t sm = mid_smem(a.g, a.TX, a.inplace);
   if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
   else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s) {
-  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.n_mid, B);
-  const size_t sm = outer_smem(a.g, a.TX);
+  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.n_mid, B * (a.g.c / outer_group(a.g)));
+  const size_t sm = outer_smem(a.g, a.TX, a.inplace);
 #define FH_L(SM, D)                                                                                          \
   switch (mode) {                                                                                            \
     case OUTER_PROJECT: hipLaunchKernelGGL((k_outer<OUTER_PROJECT, SM, D>), grid, dim3(kThreads), sm, s, a); break; \
@@ -848,6 +907,13 @@ hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int n
     case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(double* x, const double* p, const CgState* st, const Geom& g, int B, hipStream_t s) {
+  long long blk = ((long long)g.c * g.N + kThreads - 1) / kThreads;
+  if (blk > 4096) blk = 4096;
+  hipLaunchKernelGGL(k_cg_finish, dim3((unsigned)blk, B), dim3(kThreads), 0, s, x, p, st, g);
   return hipGetLastError();
 }
 
@@ -924,6 +990,11 @@ hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* pa
   hipLaunchKernelGGL((k_stress_field<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, m, packed_out, energy_out, g)
   FH_DISPATCH_MAT(mat, FH_L)
 #undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_simp_scale(const double* density, double p, double* scale, long long N, hipStream_t s) {
+  hipLaunchKernelGGL(k_simp_scale, stride_grid(N), dim3(kThreads), 0, s, density, p, scale, N);
   return hipGetLastError();
 }
 

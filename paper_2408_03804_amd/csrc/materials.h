@@ -147,6 +147,36 @@ __device__ inline void tangent_jvp_ad(const double* e, const double* de, double 
   for (int k = 0; k < C; ++k) out[k] = r.d[k].d[0];
 }
 
+// Same product, one input direction at a time: for each k, a hyper-dual pass
+// seeded with e_k (outer level) and de (inner level) gives (K : de)_k as the
+// mixed second derivative of psi.  C cheap passes over 4-double numbers
+// instead of one pass over 2(C+1)-double numbers: fewer live registers.
+template <int MAT, int NDIM>
+__device__ inline void tangent_jvp_ad_dirs(const double* e, const double* de, double lam, double mu,
+                                           double* out) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  typedef Dual<double, 1> T;
+  typedef Dual<T, 1> S;
+#pragma unroll
+  for (int k = 0; k < C; ++k) out[k] = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < C; ++k) {
+    S x[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      x[j].v.v = e[j];
+      x[j].v.d[0] = de[j];
+      x[j].d[0].v = (j == k) ? 1.0 : 0.0;
+      x[j].d[0].d[0] = 0.0;
+    }
+    const S r = Energy<MAT, NDIM, S>::psi(x, lam, mu);
+    const double val = r.d[0].d[0];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if (j == k) out[j] = val;
+  }
+}
+
 // Stress and K : de together (same nested pass; the stress is in the partials' values).
 template <int MAT, int NDIM>
 __device__ inline double stress_and_jvp_ad(const double* e, const double* de, double lam, double mu,

@@ -28,6 +28,30 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = ["xfwd_cgop", "reduce_pq", "y_fwd", "outer_project", "y_inv", "xinv_cgupdate", "reduce_rr"]
 
 
+def kernel_source_hash():
+    """sha256 of the HIP sources; HBM counter records are valid only for the sources they were taken on."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2408_03804_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel):
+    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter record, or None if stale."""
+    path = os.path.join(ROOT, "profiles", "traffic_nh3d_grf_128.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return int(k["read_bytes"] + k["write_bytes"])
+
+
 def log(msg):
     sys.stderr.write("[bench] %s\n" % msg)
     sys.stderr.flush()
@@ -105,7 +129,15 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 10 * 1e-3
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "copy_GBs": round(2 * src.numel() * 8 / t / 1e9, 1)}))
         return
     n = args.n
     w = workloads.workload_neohookean3d(n=n)
@@ -155,7 +187,7 @@ def main():
     cg_ms = float(np.sum(ms))
     iter_bytes = sum(bpv.values()) * N
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(name),
                 "kernel_ms": round(float(ms[dom]), 5),
                 "algorithmic_bytes_per_launch": int(bpv[name] * N),
                 "cg_iteration": {"ms": round(cg_ms, 5), "algorithmic_bytes": int(iter_bytes),

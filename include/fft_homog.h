@@ -160,6 +160,8 @@ int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro);
 
 void fft_homog_destroy(fft_homog_t* h);
 const char* fft_homog_strerror(int status);
+/* Message of the last failure on handle h; with h == NULL, of the last failed
+ * fft_homog_create on the calling thread. */
 const char* fft_homog_last_error(const fft_homog_t* h);
 
 /* ---- stage-level entry points (tests) --------------------------------------------------
@@ -183,10 +185,11 @@ int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, i
 /* Average device time (ms, HIP events on the handle's stream) of each kernel of one CG
  * iteration (section 3 operator, Appendix A linear solve), measured over `iters` iterations
  * of the linear solve G*(K:x) = -G*(K:E_1) at the current state, batch 1, with the
- * convergence test disabled.  ms[7] receives, in launch order: x-pass forward (K:p and
- * x-FFT), <p,K:p> reduction, y-pass forward, outer pass (z-FFT, G-hat, inverse z-FFT),
- * y-pass inverse, x-pass inverse (inverse x-FFT and CG update), <r,r> reduction (2D grids
- * report 0 for the y passes).  Leaves the strain state unchanged. */
+ * convergence test disabled.  ms[7] receives, in launch order: x-pass forward (CG vector
+ * update, K:p, x-FFT, partial <p,K:p>), <p,K:p> reduction and alpha, y-pass forward, outer
+ * pass (outer-axis FFT, G-hat, inverse FFT), y-pass inverse, x-pass inverse (inverse x-FFT,
+ * residual update, partial <r,r>), <r,r> reduction, beta and the convergence test; 2D grids
+ * report 0 for the y passes.  Leaves the strain state unchanged. */
 int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms);
 
 #ifdef __cplusplus

@@ -91,6 +91,9 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libfft_homog.so is not built (expected at %s); run "
                            "`python -m paper_2408_03804_amd.build`" % path)
+    # torch ships its own HIP runtime; load it first so that the library binds to
+    # the same runtime instance as the tensors and streams it is given
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     DP = ctypes.POINTER(ctypes.c_double)
@@ -191,7 +194,8 @@ class FFTHomog:
         rc = self.L.fft_homog_create(ctypes.byref(self.desc), ctypes.c_void_p(self._ws_ptr), nbytes,
                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if rc:
-            raise FFTHomogError(rc, "fft_homog_create")
+            msg = self.L.fft_homog_last_error(None)
+            raise FFTHomogError(rc, "fft_homog_create: " + (msg.decode() if msg else ""))
         self.h = h
 
     # ------------------------------------------------------------------ helpers

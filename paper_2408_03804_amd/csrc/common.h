@@ -11,6 +11,29 @@ constexpr int kMaxC = 9;
 constexpr int kMaxAxis = 1024;
 constexpr int kThreads = 256;
 
+// Radix schedules compiled into the FFT engine for the common axis lengths; the
+// host factorisation returns the same schedule for these lengths.
+__host__ __device__ constexpr int fixed_nstages(int n) {
+  return n == 256 ? 3 : n == 128 ? 3 : n == 64 ? 2 : n == 32 ? 2 : n == 16 ? 2 : n == 8 ? 1 : 0;
+}
+__host__ __device__ constexpr int fixed_radix(int n, int st) {
+  return n == 256 ? (st == 0 ? 8 : st == 1 ? 8 : 4)
+       : n == 128 ? (st == 0 ? 8 : 4)
+       : n == 64 ? 8
+       : n == 32 ? (st == 0 ? 8 : 4)
+       : n == 16 ? 4
+       : 8;
+}
+
+// Exact w / d for w * d < 2^32 with a precomputed multiplier m = floor(2^32 / d) + 1
+// (d = 1 has no 32-bit multiplier and is passed through).
+struct FastDiv {
+  unsigned d;
+  unsigned m;
+};
+__host__ __device__ inline FastDiv make_fastdiv(unsigned d) { return FastDiv{d, d > 1 ? 0xFFFFFFFFu / d + 1u : 0u}; }
+__device__ __forceinline__ unsigned fdiv(unsigned w, FastDiv f) { return f.d > 1 ? __umulhi(w, f.m) : w; }
+
 // Factorisation of one FFT axis into Stockham stages and its twiddle table
 // tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device memory, host-computed in
 // extended precision).

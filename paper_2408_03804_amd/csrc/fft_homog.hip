@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fft_homog.h"
+#include "fft_homog.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -35,6 +35,11 @@ int ncomp_of(int kin, int ndim) { return kin == FFT_HOMOG_SMALL_STRAIN ? (ndim =
 // Factor n into Stockham radices: 8, 4, 2 for powers of two, then 3, 5 and any
 // remaining prime factor (direct DFT stage).
 bool factorize(int n, int* radix, int* nst) {
+  if (fixed_nstages(n) > 0) {
+    *nst = fixed_nstages(n);
+    for (int st = 0; st < *nst; ++st) radix[st] = fixed_radix(n, st);
+    return true;
+  }
   int k = 0;
   int m = n;
   while (m % 8 == 0 && k < kMaxStages) { radix[k++] = 8; m /= 8; }
@@ -219,8 +224,16 @@ struct fft_homog {
 
 namespace {
 
+// message of the last failed fft_homog_create on this thread (no handle exists then)
+thread_local std::string g_create_err;
+
 int fail(fft_homog_t* h, int code, const char* msg) {
   if (h) h->err = msg ? msg : "";
+  return code;
+}
+
+int create_fail(int code, const char* what, hipError_t e) {
+  g_create_err = std::string(what) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
   return code;
 }
 
@@ -400,12 +413,13 @@ int fft_homog_workspace_size(const fft_homog_desc* d, size_t* bytes) {
 
 int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes, void* hip_stream,
                      fft_homog_t** out) {
-  if (!out) return FFT_HOMOG_EINVAL;
+  if (!out) return create_fail(FFT_HOMOG_EINVAL, "null output handle", hipSuccess);
   *out = nullptr;
   Layout L;
   int rc = make_layout(d, &L);
-  if (rc) return rc;
-  if (!dev_workspace || bytes < L.total || ((uintptr_t)dev_workspace % kAlign) != 0) return FFT_HOMOG_EWORKSPACE;
+  if (rc) return create_fail(rc, "invalid or unsupported descriptor", hipSuccess);
+  if (!dev_workspace || bytes < L.total || ((uintptr_t)dev_workspace % kAlign) != 0)
+    return create_fail(FFT_HOMOG_EWORKSPACE, "workspace too small or not 256-byte aligned", hipSuccess);
 
   fft_homog_t* h = new fft_homog();
   h->desc = *d;
@@ -432,54 +446,68 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   for (int k = 0; k < kMaxC; ++k) h->macro_cur[k] = 0.0;
   if (!h->g.small)
     for (int i = 0; i < d->ndim; ++i) h->macro_cur[i * d->ndim + i] = 1.0;
-
+  h->mat.phase = h->phase;
+  h->mat.table = h->table;
+  h->mat.scale = nullptr;
+  h->simp_p = 0.0;
   h->h_st = nullptr;
-  if (hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + kResults * sizeof(double) + 64, 0) != hipSuccess) {
+  h->ev0 = h->ev1 = nullptr;
+
+  hipError_t e = hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + kResults * sizeof(double) + 64, 0);
+  if (e != hipSuccess) {
     delete h;
-    return FFT_HOMOG_EDEVICE;
+    return create_fail(FFT_HOMOG_EDEVICE, "hipHostMalloc", e);
   }
   h->h_results = (double*)((char*)h->h_st + L.B * sizeof(CgState));
   h->h_flags = (int*)(h->h_results + kResults);
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
-    hipHostFree(h->h_st);
-    delete h;
-    return FFT_HOMOG_EDEVICE;
-  }
+  const char* step = "hipEventCreate";
+  e = hipEventCreate(&h->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&h->ev1);
 
   // twiddle tables, computed in extended precision and rounded once
-  for (int a = 0; a < d->ndim; ++a) {
+  std::vector<double2> tw[3];
+  for (int a = 0; a < d->ndim && e == hipSuccess; ++a) {
     const int n = d->n[a];
-    std::vector<double2> tw(n);
+    tw[a].resize(n);
     for (int m = 0; m < n; ++m) {
       const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
-      tw[m] = make_double2((double)cosl(ang), (double)-sinl(ang));
+      tw[a][m] = make_double2((double)cosl(ang), (double)-sinl(ang));
     }
     double2* dtw = (double2*)(h->ws + L.tw[a]);
     AxisPlan& pl = h->plan[a];
     pl.n = n;
     factorize(n, pl.radix, &pl.nstages);
     pl.tw = dtw;
-    if (hipMemcpyAsync(dtw, tw.data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess) {
-      fft_homog_destroy(h);
-      return FFT_HOMOG_EDEVICE;
-    }
+    step = "twiddle upload";
+    e = hipMemcpyAsync(dtw, tw[a].data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream);
   }
   if (h->g.ndim == 2) h->plan[2] = h->plan[1];
-
   std::vector<double> zeros(2 * kMaxPhase, 0.0);
-  if (hipMemcpyAsync(h->table, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
-          hipSuccess ||
-      hipMemsetAsync(h->phase, 0, (size_t)h->g.N, h->stream) != hipSuccess ||
-      launch_init_reference(h->F, h->g, h->stream) != hipSuccess ||
-      set_smem_limits(h->g, h->matcode, L.smem_max) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
-    fft_homog_destroy(h);
-    return FFT_HOMOG_EDEVICE;
+  if (e == hipSuccess) {
+    step = "phase table init";
+    e = hipMemcpyAsync(h->table, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   }
-  h->mat.phase = h->phase;
-  h->mat.table = h->table;
-  h->mat.scale = nullptr;
-  h->simp_p = 0.0;
+  if (e == hipSuccess) {
+    step = "phase map init";
+    e = hipMemsetAsync(h->phase, 0, (size_t)h->g.N, h->stream);
+  }
+  if (e == hipSuccess) {
+    step = "reference strain";
+    e = launch_init_reference(h->F, h->g, h->stream);
+  }
+  if (e == hipSuccess) {
+    step = "LDS limit";
+    e = set_smem_limits(h->g, h->matcode, L.smem_max);
+  }
+  if (e == hipSuccess) {
+    step = "stream synchronize";
+    e = hipStreamSynchronize(h->stream);
+  }
+  if (e != hipSuccess) {
+    fft_homog_destroy(h);
+    return create_fail(FFT_HOMOG_EDEVICE, step, e);
+  }
+  g_create_err.clear();
   *out = h;
   return FFT_HOMOG_OK;
 }
@@ -667,8 +695,8 @@ void fft_homog_destroy(fft_homog_t* h) {
   if (h->stream) hipStreamSynchronize(h->stream);
   else hipDeviceSynchronize();
   if (h->h_st) hipHostFree(h->h_st);
-  hipEventDestroy(h->ev0);
-  hipEventDestroy(h->ev1);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
   delete h;
 }
 
@@ -687,7 +715,7 @@ const char* fft_homog_strerror(int s) {
   }
 }
 
-const char* fft_homog_last_error(const fft_homog_t* h) { return h ? h->err.c_str() : ""; }
+const char* fft_homog_last_error(const fft_homog_t* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 // ---- stage-level entry points -------------------------------------------------
 static int check_batch(fft_homog_t* h, int batch) {

@@ -244,8 +244,73 @@ __device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nse
   __syncthreads();
 }
 
+// Same stage with the length, radix and stage position known at compile time
+// (no integer division except one magic multiply per element).
+template <int R, int NS, int N, int DIR>
+__device__ __forceinline__ void stage_fixed(double2* __restrict__ buf, int nseq, FastDiv fd,
+                                            const double2* __restrict__ tw) {
+  constexpr int MB = kInplaceElems / R;
+  constexpr int NB = N / R;
+  constexpr int STRIDE = N / (NS * R);
+  const int total = NB * nseq;
+  double2 v[MB][R];
+  int jv[MB], sv[MB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    jv[i] = 0;
+    sv[i] = 0;
+    if (w < total) {
+      const int j = (int)fdiv((unsigned)w, fd);
+      const int s = w - j * nseq;
+      jv[i] = j;
+      sv[i] = s;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[i][t] = buf[(j + t * NB) * nseq + s];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    if (w < total) {
+      const int j = jv[i];
+      const int s = sv[i];
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * STRIDE));
+      }
+      dft_small<R, DIR>(v[i]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[(base + t * NS) * nseq + s] = v[i][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int DIR, int ST, int NS>
+__device__ __forceinline__ void fixed_stages(double2* buf, int nseq, FastDiv fd, const double2* tw) {
+  if constexpr (ST < fixed_nstages(N)) {
+    constexpr int R = fixed_radix(N, ST);
+    stage_fixed<R, NS, N, DIR>(buf, nseq, fd, tw);
+    fixed_stages<N, DIR, ST + 1, NS * R>(buf, nseq, fd, tw);
+  }
+}
+
 template <int DIR>
 __device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
+  const FastDiv fd = make_fastdiv((unsigned)nseq);
+  switch (pl.n) {
+    case 256: fixed_stages<256, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 128: fixed_stages<128, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 64: fixed_stages<64, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 32: fixed_stages<32, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 16: fixed_stages<16, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 8: fixed_stages<8, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    default: break;
+  }
   const int n = pl.n;
   int Ns = 1;
   for (int st = 0; st < pl.nstages; ++st) {

@@ -50,6 +50,37 @@ __device__ __forceinline__ void load_lame(const MatParams& m, long long v, doubl
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // ============================================================================
+// CG scalar bookkeeping from a reduced sum (fixed-order two-stage sums)
+// ============================================================================
+template <int WHAT>
+__device__ __forceinline__ void cg_finalize(CgState& S, double s) {
+  if (WHAT == RED_SRC) {
+    S.src2 = s;
+  } else if (WHAT == RED_RHS) {
+    S.rr0 = s;
+    S.rr = s;
+    S.iters = 0;
+    S.first = 1;
+    S.beta = 0.0;
+    if (sqrt(s) <= 1e-13 * sqrt(S.src2)) S.status = CG_ZERO_RHS;
+    else if (sqrt(s) <= S.tol * sqrt(s)) S.status = CG_CONVERGED;
+    else if (S.max_iters <= 0) S.status = CG_MAXIT;
+    else S.status = CG_RUNNING;
+  } else if (WHAT == RED_PQ) {
+    S.pq = s;
+    if (!(s > 0.0)) S.status = CG_BREAKDOWN;
+    else S.alpha = S.rr / s;
+  } else {  // RED_RR
+    S.beta = s / S.rr;
+    S.rr = s;
+    S.iters += 1;
+    S.first = 0;
+    if (sqrt(s) <= S.tol * sqrt(S.rr0)) S.status = CG_CONVERGED;
+    else if (S.iters >= S.max_iters) S.status = CG_MAXIT;
+  }
+}
+
+// ============================================================================
 // x-axis forward pass
 // ============================================================================
 template <int PROD, int MAT, int NDIM>
@@ -69,6 +100,9 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   const int P = (nseq + 1) >> 1;
   extern __shared__ double2 smem[];
   double2* A = smem;
+  // CG operator: strain staged by phase A (after the FFT buffers)
+  const int nv = nr * nx;
+  double* E = reinterpret_cast<double*>(smem + (size_t)(a.inplace ? 1 : 2) * nx * P);
   double2* Bf = smem + (size_t)nx * P;  // ping-pong partner (unused in place)
   __shared__ double red[kThreads / 64];
 
@@ -90,11 +124,23 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   };
 
   if (CGOP) {
-    // phase A: CG vectors.  x += alpha_prev p_old ; p = r + beta p_old, staged in LDS
-    for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
+    // phase A: every global load of the voxel in flight together.
+    //   x += alpha_prev p_old ; p = r + beta p_old   (p staged in the FFT slots)
+    //   strain staged for phase B
+    for (int t = threadIdx.x; t < nv; t += blockDim.x) {
       const int r = t / nx;
       const int x = t - r * nx;
       const long long vox = (long long)(row0 + r) * nx + x;
+      if (PROD == PROD_CGOP && MAT != MAT_LE) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) E[j * nv + t] = a.F[j * N + vox];
+      }
+      {
+        double lam, mu;
+        load_lame(a.mat, vox, lam, mu);  // brings the phase id and table line into cache
+        (void)lam;
+        (void)mu;
+      }
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         const long long idx = ((long long)b * C + j) * N + vox;
@@ -125,13 +171,20 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       for (int j = 0; j < C; ++j) v[j] = a.in[((long long)b * C + j) * N + vox];
     } else {
       double lam, mu;
-      load_lame(a.mat, vox, lam, mu);
       double e[C];
       // the linear elastic energy is quadratic: K does not depend on the strain,
       // so the tangent passes do not read it
-      const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE && PROD != PROD_CGOP_STORED);
+      // (lam, mu) are re-read here (cache hits): staging them in LDS as well
+      // raises the register count of the fused kernel by a third
+      load_lame(a.mat, vox, lam, mu);
+      if (CGOP) {
 #pragma unroll
-      for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
+        for (int j = 0; j < C; ++j) e[j] = (PROD == PROD_CGOP && MAT != MAT_LE) ? E[j * nv + t] : 0.0;
+      } else {
+        const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE);
+#pragma unroll
+        for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
+      }
       if (PROD == PROD_STRESS) {
         if (MAT != MAT_LE) {
           const double J = det_packed<NDIM>(e);
@@ -190,8 +243,9 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 
   // separate the two real rows packed in each complex sequence
   const int nxh = g.nxh;
+  const FastDiv fdh = make_fastdiv((unsigned)nxh);
   for (int t = threadIdx.x; t < P * nxh; t += blockDim.x) {
-    const int q = t / nxh;
+    const int q = (int)fdiv((unsigned)t, fdh);
     const int k = t - q * nxh;
     const double2 zk = res[k * P + q];
     const double2 zm = res[(k == 0 ? 0 : nx - k) * P + q];
@@ -235,9 +289,24 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
   double2* A = smem;
   double2* H = smem + (size_t)nx * P;  // loaded half rows, then the ping-pong partner
   __shared__ double red[kThreads / 64];
+  const long long N = g.N;
 
+  // the residual of this thread's voxel is loaded before the transform so that
+  // its latency hides behind the FFT (one voxel per thread)
+  const bool pre = (CONS == CONS_CGUPD) && (nr * nx <= (int)blockDim.x);
+  double rpre[C];
+  if (pre && (int)threadIdx.x < nr * nx) {
+    const int r = threadIdx.x / nx;
+    const int x = threadIdx.x - r * nx;
+    const long long vox = (long long)(row0 + r) * nx + x;
+#pragma unroll
+    for (int j = 0; j < C; ++j) rpre[j] = a.r[((long long)b * C + j) * N + vox];
+  }
+
+  const FastDiv fdh = make_fastdiv((unsigned)nxh);
+  const FastDiv fdp = make_fastdiv((unsigned)P);
   for (int t = threadIdx.x; t < nseq * nxh; t += blockDim.x) {
-    const int qr = t / nxh;
+    const int qr = (int)fdiv((unsigned)t, fdh);
     const int k = t - qr * nxh;
     const int j = qr / nr;
     const int r = qr - j * nr;
@@ -245,7 +314,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
   }
   __syncthreads();
   for (int t = threadIdx.x; t < P * nx; t += blockDim.x) {
-    const int k = t / P;
+    const int k = (int)fdiv((unsigned)t, fdp);
     const int q = t - k * P;
     const int qa = 2 * q;
     const bool hb = qa + 1 < nseq;
@@ -271,7 +340,6 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
   fft_lds_any<+1>(A, H, P, a.px, a.inplace);
   const double2* res = A;
 
-  const long long N = g.N;
   double alpha = 0.0;
   if (CONS == CONS_CGUPD) alpha = a.st[b].alpha;
   double acc = 0.0;
@@ -292,7 +360,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
         a.x[idx] = 0.0;
         acc += u * u;
       } else {
-        const double rn = a.r[idx] - alpha * u;
+        const double rn = (pre ? rpre[j] : a.r[idx]) - alpha * u;
         a.r[idx] = rn;
         acc += rn * rn;
       }
@@ -332,15 +400,16 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   double2* A = smem;
   double2* Bf = smem + (size_t)ny * tw;
   const long long base = (long long)blockIdx.z * g.Nh + (long long)blockIdx.y * ny * g.nxp + kx0;
+  const FastDiv fdt = make_fastdiv((unsigned)tw);
   for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
-    const int y = t / tw;
+    const int y = (int)fdiv((unsigned)t, fdt);
     const int s = t - y * tw;
     A[t] = a.spec[base + (long long)y * g.nxp + s];
   }
   __syncthreads();
   fft_lds_any<DIR>(A, Bf, tw, a.pl, a.inplace);
   for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
-    const int y = t / tw;
+    const int y = (int)fdiv((unsigned)t, fdt);
     const int s = t - y * tw;
     a.spec[base + (long long)y * g.nxp + s] = A[t];
   }
@@ -448,10 +517,12 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
   const long long base0 = (long long)mid * g.nxp + kx0;
   const long long cbase = ((long long)b * C + grp * G) * g.Nh;
 
+  const FastDiv fdq = make_fastdiv((unsigned)nseq);
+  const FastDiv fdt = make_fastdiv((unsigned)tw);
   for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    const int o = t / nseq;
+    const int o = (int)fdiv((unsigned)t, fdq);
     const int rem = t - o * nseq;
-    const int jj = rem / tw;
+    const int jj = (int)fdiv((unsigned)rem, fdt);
     const int s = rem - jj * tw;
     D[t] = a.spec[cbase + (long long)jj * g.Nh + base0 + o * ostride + s];
   }
@@ -461,7 +532,7 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
 
   if (MODE == OUTER_PROJECT) {
     for (int t = threadIdx.x; t < n * tw; t += blockDim.x) {
-      const int o = t / tw;
+      const int o = (int)fdiv((unsigned)t, fdt);
       const int s = t - o * tw;
       double xi[NDIM];
       xi[0] = signed_freq(kx0 + s, g.nx, g.ks[0]);
@@ -509,9 +580,9 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
   if (MODE != OUTER_FWD) fft_lds_any<+1>(D, pong, nseq, a.pl, a.inplace);
 
   for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    const int o = t / nseq;
+    const int o = (int)fdiv((unsigned)t, fdq);
     const int rem = t - o * nseq;
-    const int jj = rem / tw;
+    const int jj = (int)fdiv((unsigned)rem, fdt);
     const int s = rem - jj * tw;
     a.spec[cbase + (long long)jj * g.Nh + base0 + o * ostride + s] = D[t];
   }
@@ -520,40 +591,19 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
 // ============================================================================
 // reductions of block partial sums (one block per right-hand side, fixed order)
 // ============================================================================
+// One block per right-hand side sums the block partials in a fixed order.
+constexpr int kReduceThreads = 1024;
+
 template <int WHAT>
-__global__ void __launch_bounds__(kThreads) k_cg_reduce(CgState* st, const double* partials, int nblocks) {
-  __shared__ double red[kThreads / 64];
+__global__ void __launch_bounds__(kReduceThreads) k_cg_reduce(CgState* st, const double* partials, int nblocks) {
+  __shared__ double red[kReduceThreads / 64];
   const int b = blockIdx.x;
   CgState& S = st[b];
   if ((WHAT == RED_PQ || WHAT == RED_RR) && S.status != CG_RUNNING) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[(long long)b * nblocks + i];
   const double s = block_sum(acc, red);
-  if (threadIdx.x != 0) return;
-  if (WHAT == RED_SRC) {
-    S.src2 = s;
-  } else if (WHAT == RED_RHS) {
-    S.rr0 = s;
-    S.rr = s;
-    S.iters = 0;
-    S.first = 1;
-    S.beta = 0.0;
-    if (sqrt(s) <= 1e-13 * sqrt(S.src2)) S.status = CG_ZERO_RHS;
-    else if (sqrt(s) <= S.tol * sqrt(s)) S.status = CG_CONVERGED;
-    else if (S.max_iters <= 0) S.status = CG_MAXIT;
-    else S.status = CG_RUNNING;
-  } else if (WHAT == RED_PQ) {
-    S.pq = s;
-    if (!(s > 0.0)) S.status = CG_BREAKDOWN;
-    else S.alpha = S.rr / s;
-  } else {  // RED_RR
-    S.beta = s / S.rr;
-    S.rr = s;
-    S.iters += 1;
-    S.first = 0;
-    if (sqrt(s) <= S.tol * sqrt(S.rr0)) S.status = CG_CONVERGED;
-    else if (S.iters >= S.max_iters) S.status = CG_MAXIT;
-  }
+  if (threadIdx.x == 0) cg_finalize<WHAT>(S, s);
 }
 
 __global__ void __launch_bounds__(kThreads) k_reduce_slots(const double* partials, int nblocks, double* out) {
@@ -805,7 +855,9 @@ __global__ void __launch_bounds__(kThreads) k_debug_constitutive(const double* e
 // ============================================================================
 size_t xfwd_smem(const Geom& g, int R, int inplace) {
   const int P = (g.c * R + 1) / 2;
-  return (inplace ? 1ull : 2ull) * g.nx * P * sizeof(double2);
+  const size_t fft = (inplace ? 1ull : 2ull) * g.nx * P * sizeof(double2);
+  const size_t stage = (size_t)R * g.nx * g.c * sizeof(double);
+  return fft + stage;
 }
 size_t xinv_smem(const Geom& g, int R, int inplace) {
   const int P = (g.c * R + 1) / 2;
@@ -901,10 +953,10 @@ hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s) {
 
 hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s) {
   switch (what) {
-    case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
-    case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
-    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
-    case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kThreads), 0, s, st, partials, nblocks); break;
+    case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
+    case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
+    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
+    case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -143,9 +143,15 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
  * Requires FLAG_TANGENT and a prior solve that returned OK (else ESTATE). */
 int fft_homog_tangent(fft_homog_t* h, double* C, fft_homog_stats* st);
 
-/* Gradient of J = w_energy * psi-bar + w_stress : stress-bar with respect to the per-voxel
- * density (SIMP scaling of set_material) at the last converged state.  grad_density is a
- * device f64[N].  Requires FLAG_DENSITY and a prior successful solve. */
+/* Sensitivity of a homogenized objective to the per-voxel density (the paper's section 4.4.2
+ * microstructure-optimisation use case), by the adjoint of the converged Fourier-Galerkin problem:
+ *   J = w_energy * psi-bar + sum_I w_stress[I] * out_I     (out as returned by fft_homog_solve)
+ *   solve G*(K : x) = -G*(w_energy P + K : W)              (one more CG solve, same operator)
+ *   grad_density[v] = dJ/drho_v = p / (N rho_v) * (w_energy psi_v + (W + x_v) : P_v)
+ * with W the macro tensor of the weights and lam, mu scaled by rho^p (set_material).
+ * w_stress: host f64[ncomp]; grad_density: device f64[N], layout [z][y][x].  A pure energy
+ * objective needs no CG (its right-hand side vanishes at equilibrium).  Requires a density
+ * field (FLAG_DENSITY + set_material) and a prior solve that returned OK, else ESTATE. */
 int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, double* grad_density,
                       fft_homog_stats* st);
 

@@ -21,9 +21,10 @@ materials    energy density, stress and tangent in closed form
 newton_cg    Newton-CG solve, homogenized stress/energy and homogenized tangent
 bruteforce   dense displacement-formulation solve for tiny grids (independent of G and CG)
 closed_forms isotropic stiffness, exact laminate, Voigt/Reuss bounds
+adjoint      gradient of homogenized energy/stress w.r.t. a per-voxel SIMP density
 
 Parity status: every function above is pinned by the CPU tests in
 ``tests/test_oracle_pins.py``; none is "parity unpinned".
 """
 
-from . import spectral, materials, newton_cg, bruteforce, closed_forms  # noqa: F401
+from . import spectral, materials, newton_cg, bruteforce, closed_forms, adjoint  # noqa: F401

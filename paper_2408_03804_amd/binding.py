@@ -251,6 +251,17 @@ class FFTHomog:
         self._check(rc, allow)
         return C, st.as_dict()
 
+    def reset(self):
+        """Back to the undeformed reference state (eps = 0 / F = I) with zero macro load."""
+        d = self.ndim
+        ref = self.torch.zeros((d * d,) + self.shape, dtype=self.torch.float64, device=self.device)
+        macro = np.zeros(self.c)
+        if self.kinematics != "small":
+            for i in range(d):
+                ref[i * d + i] = 1.0
+            macro = np.eye(d).reshape(-1)
+        self.set_field(ref, macro)
+
     def adjoint(self, w_stress, w_energy):
         w = np.ascontiguousarray(w_stress, dtype=np.float64)
         g = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)

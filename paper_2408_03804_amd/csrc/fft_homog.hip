@@ -657,12 +657,55 @@ int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
 }
 
 int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, double* grad_density,
-                      fft_homog_stats* st) {
-  (void)w_stress;
-  (void)w_energy;
-  (void)grad_density;
-  (void)st;
-  return fail(h, FFT_HOMOG_EUNSUPPORTED, "adjoint not built");
+                      fft_homog_stats* stats) {
+  if (!h || !w_stress || !grad_density) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (!h->mat.scale) return fail(h, FFT_HOMOG_ESTATE, "no density field set (FLAG_DENSITY and set_material)");
+  if (!h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
+  if (!std::isfinite(w_energy)) return fail(h, FFT_HOMOG_EINVAL, "non-finite weight");
+  const int C = h->g.c;
+  for (int k = 0; k < C; ++k)
+    if (!std::isfinite(w_stress[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite weight");
+  fft_homog_stats S;
+  memset(&S, 0, sizeof(S));
+  FH_CK(hipEventRecord(h->ev0, h->stream));
+  // W in the packed basis: the objective is sum_I w_I out_I with out_I = W-packed . P-packed
+  double W[kMaxC];
+  from_packed_stress(h, w_stress, W);
+  XFwdArgs a = xfwd_args(h);
+  for (int k = 0; k < C; ++k) a.unit[k] = W[k];
+  a.w_energy = w_energy;
+  int rc = upload_states(h, 1);
+  if (rc) return rc;
+  FH_CK(launch_xfwd(PROD_ADJ, h->matcode, a, 1, h->stream));
+  FH_CK(launch_cg_reduce(RED_SRC, h->st, h->partials, h->L.nblk_x, 1, h->stream));
+  rc = spectral_middle(h, OUTER_PROJECT, 1, nullptr);
+  if (rc) return rc;
+  FH_CK(launch_xinv(CONS_RHS, xinv_args(h), 1, h->stream));
+  FH_CK(launch_cg_reduce(RED_RHS, h->st, h->partials, h->L.nblk_x, 1, h->stream));
+  rc = read_states(h, 1);
+  if (rc) return rc;
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+  rc = cg_loop(h, 1);
+  if (rc) return rc;
+  const CgState& cs = h->h_st[0];
+  int status = FFT_HOMOG_OK;
+  if (cs.status == CG_BREAKDOWN) status = FFT_HOMOG_EBREAKDOWN;
+  else if (cs.status == CG_MAXIT) status = FFT_HOMOG_ENOTCONV;
+  S.cg_iterations = cs.iters;
+  S.n_recorded = 1;
+  S.cg_per_newton[0] = cs.iters;
+  S.cg_residual = cs.rr0 > 0 ? std::sqrt(cs.rr / cs.rr0) : 0.0;
+  FH_CK(launch_simp_gradient(h->matcode, h->F, h->x, h->mat, h->density, h->simp_p, W, w_energy, grad_density, h->g,
+                             h->stream));
+  FH_CK(hipEventRecord(h->ev1, h->stream));
+  FH_CK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  S.seconds = ms * 1e-3;
+  S.status = status;
+  if (stats) *stats = S;
+  if (status) h->err = status == FFT_HOMOG_EBREAKDOWN ? "CG breakdown" : "iteration limit reached";
+  return status;
 }
 
 int fft_homog_get_field(fft_homog_t* h, int which, double* dst) {

@@ -5,7 +5,7 @@
 
 namespace fh {
 
-enum Producer { PROD_IDENT = 0, PROD_STRESS = 1, PROD_CGOP = 2, PROD_TRHS = 3, PROD_CGOP_STORED = 4 };
+enum Producer { PROD_IDENT = 0, PROD_STRESS = 1, PROD_CGOP = 2, PROD_TRHS = 3, PROD_CGOP_STORED = 4, PROD_ADJ = 5 };
 enum Consumer { CONS_IDENT = 0, CONS_RHS = 1, CONS_CGUPD = 2 };
 enum OuterMode { OUTER_PROJECT = 0, OUTER_FWD = 1, OUTER_INV = 2 };
 enum Reduce { RED_SRC = 0, RED_RHS = 1, RED_PQ = 2, RED_RR = 3 };
@@ -26,7 +26,8 @@ struct XFwdArgs {
   MatParams mat;
   CgState* st;           // per right-hand side
   double* partials;      // [B][nblocks]
-  double unit[kMaxC];    // TRHS: unit load b is unit[b] * e_b in the packed basis
+  double unit[kMaxC];    // TRHS: unit load b is unit[b] * e_b in the packed basis; ADJ: packed W
+  double w_energy;       // ADJ: weight of the energy in the objective
 };
 
 // x-axis inverse pass: complex-to-real FFT along x, then per-voxel consumer.
@@ -92,6 +93,10 @@ hipError_t launch_simp_scale(const double* density, double p, double* scale, lon
 hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s);
 hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE,
                                      double* psi, MatParams m, const Geom& g, hipStream_t s);
+// dJ/drho_v = p / (N rho_v) [ w_e psi_v + (W + x_v) : P_v ]  (adjoint density gradient)
+hipError_t launch_simp_gradient(int mat, const double* F, const double* x, MatParams m, const double* density,
+                                double p, const double* W, double w_energy, double* grad, const Geom& g,
+                                hipStream_t s);
 hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes);
 
 }  // namespace fh

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) e[j] = (PROD == PROD_CGOP && MAT != MAT_LE) ? E[j * nv + t] : 0.0;
       } else {
-        const bool need_e = (PROD == PROD_STRESS) || (MAT != MAT_LE);
+        const bool need_e = (PROD == PROD_STRESS) || (PROD == PROD_ADJ) || (MAT != MAT_LE);
 #pragma unroll
         for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
       }
@@ -195,6 +195,17 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         for (int j = 0; j < C; ++j) {
           acc += v[j] * v[j];
           if (!isfinite(v[j])) bad = 1;
+        }
+      } else if (PROD == PROD_ADJ) {
+        // objective gradient with respect to the strain: g = w_e P + K : W
+        double P[C], W[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) W[j] = a.unit[j];
+        stress_and_jvp_ad<MAT, NDIM>(e, W, lam, mu, P, v);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          v[j] += a.w_energy * P[j];
+          acc += v[j] * v[j];
         }
       } else if (PROD == PROD_TRHS) {
         double de[C];
@@ -816,6 +827,27 @@ __global__ void __launch_bounds__(kThreads) k_stress_field(const double* F, MatP
   if (energy_out != nullptr) energy_out[v] = psi;
 }
 
+// Adjoint density gradient.  With lam, mu scaled by rho^p, d psi/d rho = (p/rho) psi and
+// d P/d rho = (p/rho) P at fixed strain; x solves G*(K:x) = -G*(w_e P + K:W).
+template <int MAT, int NDIM>
+__global__ void __launch_bounds__(kThreads) k_simp_gradient(const double* F, const double* x, MatParams m,
+                                                            const double* density, double p, Small9 W,
+                                                            double w_energy, double* grad, Geom g) {
+  constexpr int C = MatTraits<MAT, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], P[C], lam, mu;
+#pragma unroll
+  for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+  load_lame(m, v, lam, mu);
+  const double psi = stress_ad<MAT, NDIM>(e, lam, mu, P);
+  double wp = w_energy * psi;
+#pragma unroll
+  for (int j = 0; j < C; ++j) wp += (W.v[j] + x[j * N + v]) * P[j];
+  grad[v] = p / ((double)N * density[v]) * wp;
+}
+
 // scale[v] = density[v]^p (SIMP interpolation of the Lame parameters)
 __global__ void k_simp_scale(const double* density, double p, double* scale, long long N) {
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x)
@@ -896,6 +928,7 @@ hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t 
     case PROD_TRHS: hipLaunchKernelGGL((k_xfwd<PROD_TRHS, M, D>), grid, dim3(kThreads), sm, s, a); break;     \
     case PROD_CGOP_STORED:                                                                               \
       hipLaunchKernelGGL((k_xfwd<PROD_CGOP_STORED, M, D>), grid, dim3(kThreads), sm, s, a); break;       \
+    case PROD_ADJ: hipLaunchKernelGGL((k_xfwd<PROD_ADJ, M, D>), grid, dim3(kThreads), sm, s, a); break;       \
     default: return hipErrorInvalidValue;                                                                \
   }
   FH_DISPATCH_MAT(mat, FH_L)
@@ -1045,6 +1078,19 @@ hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* pa
   return hipGetLastError();
 }
 
+hipError_t launch_simp_gradient(int mat, const double* F, const double* x, MatParams m, const double* density,
+                                double p, const double* W, double w_energy, double* grad, const Geom& g,
+                                hipStream_t s) {
+  Small9 w;
+  for (int k = 0; k < kMaxC; ++k) w.v[k] = k < g.c ? W[k] : 0.0;
+#define FH_L(M, D)                                                                                          \
+  hipLaunchKernelGGL((k_simp_gradient<M, D>), vox_grid(g), dim3(kThreads), 0, s, F, x, m, density, p, w, \
+                     w_energy, grad, g)
+  FH_DISPATCH_MAT(mat, FH_L)
+#undef FH_L
+  return hipGetLastError();
+}
+
 hipError_t launch_simp_scale(const double* density, double p, double* scale, long long N, hipStream_t s) {
   hipLaunchKernelGGL(k_simp_scale, stride_grid(N), dim3(kThreads), 0, s, density, p, scale, N);
   return hipGetLastError();
@@ -1076,7 +1122,8 @@ hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes) {
   FH_SET((k_xfwd<PROD_STRESS, M, D>));              \
   FH_SET((k_xfwd<PROD_CGOP, M, D>));                \
   FH_SET((k_xfwd<PROD_TRHS, M, D>));                \
-  FH_SET((k_xfwd<PROD_CGOP_STORED, M, D>));
+  FH_SET((k_xfwd<PROD_CGOP_STORED, M, D>));         \
+  FH_SET((k_xfwd<PROD_ADJ, M, D>));
   FH_DISPATCH_MAT(mat, FH_L)
 #undef FH_L
 #define FH_X(CC) FH_SET((k_xinv<CONS_IDENT, CC>)); FH_SET((k_xinv<CONS_RHS, CC>)); FH_SET((k_xinv<CONS_CGUPD, CC>));

@@ -448,3 +448,64 @@ def test_pins_detect_planted_mistakes(monkeypatch):
 
     monkeypatch.setattr(nh, "tangent_apply", staticmethod(bad_tangent))
     assert tangent_complex_step_error(nh, F, dF, lam, mu) > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# adjoint density gradient (oracle) against finite differences of full solves
+# ----------------------------------------------------------------------------
+from oracle import adjoint  # noqa: E402
+
+
+def _simp_problem(shape, material, table, phase, rho, p):
+    lam0, mu0 = _two_phase(phase, table)
+    s = rho ** p
+    return newton_cg.Problem(shape, material, lam0 * s, mu0 * s)
+
+
+@pytest.mark.parametrize("material,shape", [("neo_hookean", (5, 4)), ("neo_hookean", (3, 4, 3)),
+                                            ("linear_elastic", (4, 5)), ("stvk", (3, 3, 4))])
+def test_adjoint_gradient_matches_finite_differences(material, shape):
+    d = len(shape)
+    rng = np.random.default_rng(21)
+    table = [[1.0, 1.0], [4.0, 3.0]]
+    phase = workloads.random_phases(shape, 2, 22)
+    rho = rng.uniform(0.3, 1.0, shape)
+    p = 3.0
+    prob = _simp_problem(shape, material, table, phase, rho, p)
+    if prob.kinematics == "small":
+        macro = 0.01 * rng.standard_normal(3 if d == 2 else 6)
+        ncomp = len(macro)
+    else:
+        macro = (np.eye(d) + 0.04 * rng.standard_normal((d, d))).reshape(-1)
+        ncomp = d * d
+    w_s = rng.standard_normal(ncomp)
+    w_e = 0.7
+    kw = dict(n_increments=1, tol_newton=1e-13, tol_cg=1e-14)
+    ref = newton_cg.solve(prob, macro, **kw)
+    grad, k = adjoint.simp_gradient(prob, ref["state"], rho, p, w_s, w_e, tol_cg=1e-14)
+    assert k > 0
+    h = 1e-5
+    for v in [(0,) * d, tuple(s - 1 for s in shape), tuple(s // 2 for s in shape)]:
+        vals = []
+        for sgn in (1.0, -1.0):
+            r2 = rho.copy()
+            r2[v] += sgn * h
+            pr = _simp_problem(shape, material, table, phase, r2, p)
+            st = newton_cg.solve(pr, macro, **kw)["state"]
+            vals.append(adjoint.objective(pr, st, w_s, w_e))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - grad[v]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(grad).max())
+
+
+def test_adjoint_energy_gradient_is_envelope_form():
+    shape = (4, 3, 5)
+    rng = np.random.default_rng(23)
+    phase = workloads.random_phases(shape, 2, 24)
+    rho = rng.uniform(0.2, 1.0, shape)
+    prob = _simp_problem(shape, "neo_hookean", [[1.0, 1.0], [5.0, 2.0]], phase, rho, 3.0)
+    F = np.eye(3) + 0.03 * rng.standard_normal((3, 3))
+    ref = newton_cg.solve(prob, F.reshape(-1), tol_newton=1e-13, tol_cg=1e-14)
+    grad, k = adjoint.simp_gradient(prob, ref["state"], rho, 3.0, np.zeros(9), 1.0)
+    assert k == 0
+    psi = prob.energy_density(ref["state"].field)
+    assert rel(grad, 3.0 * psi / (prob.N * rho)) < 1e-13

@@ -105,6 +105,36 @@ __device__ __forceinline__ void dft8(double2* v) {
   }
 }
 
+// 16-point DFT as 4 x 4: DFTs over n1 of x[4 n1 + n2], twiddle by w16^(n2 k1),
+// DFTs over n2; output k1 + 4 k2.  Twiddles are compile-time constants.
+template <int DIR>
+__device__ __forceinline__ void dft16(double2* v) {
+  constexpr double C16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                              0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  double2 y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    double2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft4<DIR>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      const int m = (n2 * k1) & 15;
+      const double c = C16[m];
+      const double sn = DIR * C16[(m + 12) & 15];  // sin(2 pi m / 16) = cos(2 pi (m - 4) / 16)
+      y[n2][k1] = (m == 0) ? t[k1] : make_double2(t[k1].x * c - t[k1].y * sn, t[k1].x * sn + t[k1].y * c);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    double2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4<DIR>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft_small(double2* v) {
   if constexpr (R == 2) dft2<DIR>(v);
@@ -112,6 +142,7 @@ __device__ __forceinline__ void dft_small(double2* v) {
   else if constexpr (R == 4) dft4<DIR>(v);
   else if constexpr (R == 5) dft5<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
+  else if constexpr (R == 16) dft16<DIR>(v);
 }
 
 // One Stockham stage of radix R for all sequences.
@@ -187,6 +218,7 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
       case 4: stage_small<4, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
       case 5: stage_small<5, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
       case 8: stage_small<8, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
+      case 16: stage_small<16, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
       default: stage_generic<DIR>(src, dst, nseq, n, Ns, R, pl.tw); break;
     }
     __syncthreads();
@@ -320,6 +352,7 @@ __device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
       case 3: stage_inplace<3, DIR>(buf, nseq, n, Ns, pl.tw); break;
       case 4: stage_inplace<4, DIR>(buf, nseq, n, Ns, pl.tw); break;
       case 5: stage_inplace<5, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      case 16: stage_inplace<16, DIR>(buf, nseq, n, Ns, pl.tw); break;
       default: stage_inplace<8, DIR>(buf, nseq, n, Ns, pl.tw); break;
     }
     Ns *= R;

@@ -907,7 +907,7 @@ size_t outer_smem(const Geom& g, int TX, int inplace) {
 bool inplace_ok(const AxisPlan& pl, int nseq) {
   for (int st = 0; st < pl.nstages; ++st) {
     const int R = pl.radix[st];
-    if (R != 2 && R != 3 && R != 4 && R != 5 && R != 8) return false;
+    if (R != 2 && R != 3 && R != 4 && R != 5 && R != 8 && R != 16) return false;
     const long long total = (long long)nseq * (pl.n / R);
     const long long per_thread = (total + kThreads - 1) / kThreads;
     if (per_thread > kInplaceElems / R) return false;

@@ -15,7 +15,9 @@ from paper_2408_03804_amd import workloads
 pytestmark = pytest.mark.gpu
 
 MATS = [("linear_elastic", "small"), ("neo_hookean", "finite"), ("stvk", "finite")]
-FFT_SHAPES = [(7, 5), (31, 31), (8, 12), (1, 9), (6, 10, 12), (9, 16, 15), (5, 6, 7), (3, 4, 1), (13, 11, 17)]
+FFT_SHAPES = [(7, 5), (31, 31), (8, 12), (1, 9), (6, 10, 12), (9, 16, 15), (5, 6, 7), (3, 4, 1), (13, 11, 17),
+              # lengths with compiled-in radix schedules (16, 8, 8.4, 16.8, 16.16) on every axis
+              (2, 4, 128), (128, 3, 2), (3, 256, 2), (16, 32, 64), (64, 16, 32), (256, 6), (5, 256)]
 
 
 def make(shape, kin, mat, nphase=2, **kw):
@@ -67,7 +69,8 @@ def test_rfft_and_irfft_match_numpy(shape):
 
 @pytest.mark.parametrize("kin,mat", [("small", "linear_elastic"), ("finite", "neo_hookean")])
 @pytest.mark.parametrize("shape,lengths", [((7, 9), (1.0, 1.3)), ((31, 31), None), ((6, 8), None),
-                                           ((5, 6, 7), (1.0, 0.8, 1.2)), ((8, 12, 10), None), ((9, 16, 15), None)])
+                                           ((5, 6, 7), (1.0, 0.8, 1.2)), ((8, 12, 10), None), ((9, 16, 15), None),
+                                           ((128, 4, 6), None), ((6, 128, 32), None)])
 def test_projection_matches_oracle(kin, mat, shape, lengths):
     d = len(shape)
     h = make(shape, kin, mat, lengths=lengths)

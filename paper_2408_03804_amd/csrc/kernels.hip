@@ -49,6 +49,12 @@ __device__ __forceinline__ void load_lame(const MatParams& m, long long v, doubl
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Streaming access for the CG vectors and the linearisation point: each is touched once
+// per CG iteration, so keeping them out of the caches leaves room for the half spectrum
+// that the FFT passes hand to each other.
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 // ============================================================================
 // CG scalar bookkeeping from a reduced sum (fixed-order two-stage sums)
 // ============================================================================
@@ -133,7 +139,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       const long long vox = (long long)(row0 + r) * nx + x;
       if (PROD == PROD_CGOP && MAT != MAT_LE) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) E[j * nv + t] = a.F[j * N + vox];
+        for (int j = 0; j < C; ++j) E[j * nv + t] = ld_stream(a.F + j * N + vox);
       }
       {
         double lam, mu;
@@ -144,16 +150,16 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         const long long idx = ((long long)b * C + j) * N + vox;
-        const double rj = a.in[idx];
+        const double rj = ld_stream(a.in + idx);
         double pj;
         if (first) {
           pj = rj;
         } else {
-          const double po = a.p[idx];
-          a.x[idx] += alpha_prev * po;
+          const double po = ld_stream(a.p + idx);
+          st_stream(a.x + idx, ld_stream(a.x + idx) + alpha_prev * po);
           pj = rj + beta * po;
         }
-        a.p[idx] = pj;
+        st_stream(a.p + idx, pj);
         *slot(j, r, x) = pj;
       }
     }
@@ -311,7 +317,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
     const int x = threadIdx.x - r * nx;
     const long long vox = (long long)(row0 + r) * nx + x;
 #pragma unroll
-    for (int j = 0; j < C; ++j) rpre[j] = a.r[((long long)b * C + j) * N + vox];
+    for (int j = 0; j < C; ++j) rpre[j] = ld_stream(a.r + ((long long)b * C + j) * N + vox);
   }
 
   const FastDiv fdh = make_fastdiv((unsigned)nxh);
@@ -371,8 +377,8 @@ __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
         a.x[idx] = 0.0;
         acc += u * u;
       } else {
-        const double rn = (pre ? rpre[j] : a.r[idx]) - alpha * u;
-        a.r[idx] = rn;
+        const double rn = (pre ? rpre[j] : ld_stream(a.r + idx)) - alpha * u;
+        st_stream(a.r + idx, rn);
         acc += rn * rn;
       }
     }

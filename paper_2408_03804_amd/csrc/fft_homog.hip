@@ -27,6 +27,7 @@ constexpr int kChunk = 8;          // CG iterations enqueued between host checks
 constexpr size_t kLdsFft = 48 * 1024;
 constexpr size_t kLdsOuter = 64 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kOuterTileMax = 4;   // kx bins per outer-pass block (measured best at 128^3)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -151,7 +152,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   for (int t = 16; t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
     const int ip = inplace_ok(pouter, G * t) ? 1 : 0;
-    if (outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }
+    if (t <= kOuterTileMax && outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }
   }
   if (TXo == 0) {
     TXo = 1;

@@ -518,12 +518,26 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
   constexpr int G = SMALL ? C : NDIM;
   constexpr int NGRP = C / G;
   const Geom& g = a.g;
-  const int b = blockIdx.z / NGRP;
-  const int grp = blockIdx.z - b * NGRP;
+  // Consecutive blocks are dealt round-robin to the 8 XCDs.  Re-index so that
+  // the tiles of one spectrum row (which share 128-byte lines when TX < 8) run
+  // on the same XCD, close in time, and meet in its L2.
+  unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  {
+    const unsigned tot = gridDim.x * gridDim.y * gridDim.z;
+    if ((tot & 7u) == 0u) {
+      const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      const unsigned l2 = (lin & 7u) * (tot >> 3) + (lin >> 3);
+      bx = l2 % gridDim.x;
+      by = (l2 / gridDim.x) % gridDim.y;
+      bz = l2 / (gridDim.x * gridDim.y);
+    }
+  }
+  const int b = bz / NGRP;
+  const int grp = bz - b * NGRP;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
-  const int kx0 = blockIdx.x * a.TX;
+  const int kx0 = bx * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
-  const int mid = blockIdx.y;
+  const int mid = by;
   const int n = g.n_outer;
   const int nseq = G * tw;
   const int cnt = n * nseq;

@@ -69,6 +69,9 @@ enum { FFT_HOMOG_K_RECOMPUTE = 0, FFT_HOMOG_K_STORED = 1 };
 /* flags */
 #define FFT_HOMOG_FLAG_TANGENT 1u  /* size the workspace for the ncomp-RHS tangent solve */
 #define FFT_HOMOG_FLAG_DENSITY 2u  /* reserve a per-voxel density field (SIMP scaling) */
+#define FFT_HOMOG_FLAG_GRAPH 4u    /* enqueue full chunks of CG iterations by replaying a captured
+                                      HIP graph (built on first use, rebuilt after set_material or
+                                      autotune); results are bitwise those of direct launches */
 
 enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_ENERGY = 2 };
 
@@ -85,6 +88,13 @@ typedef struct fft_homog_desc {
   int max_cg;        /* per linear solve */
   int k_mode;        /* FFT_HOMOG_K_RECOMPUTE or FFT_HOMOG_K_STORED */
   unsigned flags;    /* FFT_HOMOG_FLAG_* */
+  int batch;         /* independent cells of this grid held by the handle (0 or 1: one cell).
+                        batch > 1 makes a multi-cell handle: it needs FLAG_TANGENT and
+                        K_RECOMPUTE, takes no FLAG_DENSITY, and computes the homogenized tangent
+                        of every cell at the reference state (eps = 0, F = I) with all
+                        batch * ncomp linear solves in the same launches; solve, adjoint,
+                        get_field and set_field return EUNSUPPORTED on it.  batch * ncomp^2
+                        must not exceed 65535 (EUNSUPPORTED). */
 } fft_homog_desc;
 
 #define FFT_HOMOG_MAX_RECORDED 256
@@ -121,7 +131,9 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
 
 /* Microstructure (the two-phase RVEs of section 4: per-phase Lame parameters).
  *   phase            device u8[N], layout [z][y][x]; copied into the workspace.
+ *                    Multi-cell handle: u8[batch][N], the cells back to back.
  *   phase_lambda_mu  host f64[nphase][2] = (lam, mu) per phase.
+ *                    Multi-cell handle: f64[batch][nphase][2], one table per cell.
  *   density          device f64[N] or NULL; when given (requires FLAG_DENSITY), lam and mu of
  *                    voxel v are scaled by density[v]^simp_p.
  * EINVAL if a phase id is >= nphase (checked on the device before returning). */
@@ -140,7 +152,10 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
 /* Homogenized tangent at the last converged state (section 3.3): host f64[ncomp][ncomp],
  * C_IJ = < (E_I + x_I) : K : (E_J + x_J) > with x_I solving G*(K:x_I) = -G*(K:E_I) for the
  * unit macro loads E_I; all ncomp linear solves run batched in the same launches.
- * Requires FLAG_TANGENT and a prior solve that returned OK (else ESTATE). */
+ * Requires FLAG_TANGENT and a prior solve that returned OK (else ESTATE).
+ * Multi-cell handle (desc.batch > 1): C is host f64[batch][ncomp][ncomp], each cell's tangent
+ * at the reference state; no prior solve is needed.  stats.cg_per_newton lists the CG
+ * iterations of the first 256 linear solves (cell-major, load index fastest). */
 int fft_homog_tangent(fft_homog_t* h, double* C, fft_homog_stats* st);
 
 /* Sensitivity of a homogenized objective to the per-voxel density (the paper's section 4.4.2
@@ -163,6 +178,22 @@ int fft_homog_get_field(fft_homog_t* h, int which, double* dst);
 /* Restart from a given state: src device f64[d*d][N] full tensors, macro host f64[ncomp] the
  * macro load that state belongs to (its voxel average).  Small strain takes the symmetric part. */
 int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro);
+
+/* Launch shape of the CG passes: shape[0] lines per x-pass block, shape[1] kx bins per
+ * y-pass block, shape[2] kx bins per outer-pass block, shape[3..5] 1 if the x, y and outer
+ * FFT stages are staged through registers (one LDS buffer) rather than ping-ponged. */
+int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[6]);
+
+/* Time every candidate launch shape of the CG passes on this handle's grid and batch
+ * (each pass over `reps` launches after one warm-up, HIP events on the handle's stream) and
+ * keep the fastest per pass; the chosen shape is written to shape[6] (nullable) in the layout
+ * of fft_homog_get_launch_shape.  The candidates are the x-pass block heights that fit the
+ * default 64 KiB per-block LDS limit, with and without register staging, and 1..16 (y) or 1..8 (outer)
+ * kx bins per block.  The CG work vectors are overwritten; the strain state, the material
+ * and the last tangent's inputs are kept, so it may be called between any two calls.
+ * Results of later solves agree with those of the default shape to rounding (the block
+ * height changes the order of the partial sums). */
+int fft_homog_autotune(fft_homog_t* h, int reps, int shape[6]);
 
 void fft_homog_destroy(fft_homog_t* h);
 const char* fft_homog_strerror(int status);

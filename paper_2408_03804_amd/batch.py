@@ -1,0 +1,114 @@
+"""Homogenized tangents of many cells of uneven grid size.
+
+Cells are grouped by grid shape.  Each group runs on multi-cell handles
+(``desc.batch`` > 1): the ncomp unit-load tangent solves of every cell in a
+chunk share each launch of the CG passes, so small grids still fill the GPU.
+A group is split into chunks whose workspace fits ``max_bytes``.  Handles are
+cached per (shape, chunk size); with ``graph`` the CG iterations replay a
+captured HIP graph and with ``autotune`` each new handle picks its launch shape
+by timing the candidates once.  Argument marshalling only: all arithmetic runs
+in the HIP library.
+"""
+
+from collections import OrderedDict
+
+import numpy as np
+
+from . import binding
+
+MAX_CELLS_PER_LAUNCH = 65535
+
+
+class TangentBatcher:
+    def __init__(self, kinematics="small", material="linear_elastic", nphase=2, tol_cg=1e-10, max_cg=20000,
+                 max_bytes=64 << 30, graph=True, autotune=True, device=None, stream=None):
+        self.kinematics = kinematics
+        self.material = material
+        self.nphase = int(nphase)
+        self.kw = dict(tol_cg=tol_cg, max_cg=max_cg, tangent=True, graph=graph)
+        self.max_bytes = int(max_bytes)
+        self.autotune = autotune
+        self.device = device
+        self.stream = stream
+        self.handles = OrderedDict()
+        self.shapes = {}
+
+    def _ncomp(self, shape):
+        d = len(shape)
+        return (3 if d == 2 else 6) if self.kinematics == "small" else d * d
+
+    def chunk_size(self, shape, n):
+        """Largest number of cells (<= n) of this shape whose workspace fits max_bytes."""
+        c = self._ncomp(shape)
+        hi = max(1, min(n, MAX_CELLS_PER_LAUNCH // (c * c)))
+
+        def size(k):
+            d = binding.make_desc(shape, self.kinematics, self.material, self.nphase, batch=k, **self.kw)
+            return binding.fft_homog_workspace_size(d)
+
+        if size(1) > self.max_bytes:
+            raise ValueError("one cell of shape %s needs more than max_bytes" % (shape,))
+        lo = 1
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if size(mid) <= self.max_bytes:
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
+
+    def handle(self, shape, k):
+        key = (tuple(shape), int(k))
+        h = self.handles.get(key)
+        if h is None:
+            h = binding.FFTHomog(shape, self.kinematics, self.material, self.nphase, device=self.device,
+                                 stream=self.stream, batch=k, **self.kw)
+            self.handles[key] = h
+            self._tune = key if self.autotune else None
+        return h
+
+    def tangents(self, cells):
+        """cells: sequence of dicts with 'phase' (grid array) and 'table' ((nphase, 2) lam, mu).
+
+        Returns (C, info): C is an array (len(cells), c, c) when every cell has the same c
+        (otherwise a list), info a list of per-chunk records (shape, cells, cg total, seconds).
+        """
+        import torch
+
+        groups = OrderedDict()
+        for i, cell in enumerate(cells):
+            groups.setdefault(tuple(np.shape(cell["phase"])), []).append(i)
+        out = [None] * len(cells)
+        info = []
+        for shape, idx in groups.items():
+            k = self.chunk_size(shape, len(idx))
+            for s in range(0, len(idx), k):
+                chunk = idx[s:s + k]
+                self._tune = None
+                h = self.handle(shape, len(chunk))
+                phase = torch.stack([torch.as_tensor(np.asarray(cells[i]["phase"], dtype=np.uint8))
+                                     for i in chunk]).to(h.device)
+                table = np.stack([np.asarray(cells[i]["table"], dtype=np.float64) for i in chunk])
+                h.set_material(phase, table)
+                if self._tune is not None:
+                    self.shapes[self._tune] = h.autotune()
+                if h.cells == 1:
+                    # a one-cell handle takes its tangent at a converged state: the reference
+                    # state is one (zero load, no CG)
+                    d = len(shape)
+                    h.reset()
+                    h.solve(np.eye(d).reshape(-1) if self.kinematics == "finite" else np.zeros(h.c), 1)
+                C, st = h.tangent()
+                C = C.reshape(len(chunk), h.c, h.c)
+                for j, i in enumerate(chunk):
+                    out[i] = C[j]
+                info.append(dict(shape=shape, cells=len(chunk), cg_total=st["cg_total"], seconds=st["seconds"],
+                                 status=st["status"]))
+        if len({o.shape for o in out}) == 1:
+            out = np.stack(out)
+        return out, info
+
+    def close(self):
+        for h in self.handles.values():
+            h.close()
+        self.handles.clear()

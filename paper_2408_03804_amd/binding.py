@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfft_homog.so")
 SMALL_STRAIN, FINITE_STRAIN = 0, 1
 LINEAR_ELASTIC, NEO_HOOKEAN, STVK = 0, 1, 2
 K_RECOMPUTE, K_STORED = 0, 1
-FLAG_TANGENT, FLAG_DENSITY = 1, 2
+FLAG_TANGENT, FLAG_DENSITY, FLAG_GRAPH = 1, 2, 4
 FIELD_STRAIN, FIELD_STRESS, FIELD_ENERGY = 0, 1, 2
 MAX_RECORDED = 256
 
@@ -43,6 +43,7 @@ class Desc(ctypes.Structure):
         ("max_cg", ctypes.c_int),
         ("k_mode", ctypes.c_int),
         ("flags", ctypes.c_uint),
+        ("batch", ctypes.c_int),
     ]
 
 
@@ -78,6 +79,7 @@ EXPORTS = [
     "fft_homog_destroy", "fft_homog_strerror", "fft_homog_last_error",
     "fft_homog_debug_constitutive", "fft_homog_debug_rfft", "fft_homog_debug_irfft",
     "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_time_cg",
+    "fft_homog_get_launch_shape", "fft_homog_autotune",
 ]
 
 _lib = None
@@ -115,6 +117,8 @@ def load_library(path=LIB_PATH):
         "fft_homog_debug_project": (I, [P, P, P, I]),
         "fft_homog_debug_apply_operator": (I, [P, P, P, I]),
         "fft_homog_debug_time_cg": (I, [P, I, DP]),
+        "fft_homog_get_launch_shape": (I, [P, ctypes.POINTER(I)]),
+        "fft_homog_autotune": (I, [P, I, ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -131,6 +135,10 @@ class FFTHomogError(RuntimeError):
         self.status = STATUS.get(code, str(code))
 
 
+def _shape_dict(s):
+    return {"x_rows": s[0], "y_bins": s[1], "outer_bins": s[2], "x_regs": s[3], "y_regs": s[4], "outer_regs": s[5]}
+
+
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -140,7 +148,8 @@ def _tptr(t):
 
 
 def make_desc(shape, kinematics, material, nphase, tol_newton=1e-10, tol_cg=1e-10, max_newton=50,
-              max_cg=10000, k_mode=K_RECOMPUTE, tangent=False, density=False, lengths=None):
+              max_cg=10000, k_mode=K_RECOMPUTE, tangent=False, density=False, lengths=None, graph=False,
+              batch=1):
     d = Desc()
     shape = tuple(int(s) for s in shape)
     d.ndim = len(shape)
@@ -156,7 +165,8 @@ def make_desc(shape, kinematics, material, nphase, tol_newton=1e-10, tol_cg=1e-1
     d.max_newton = int(max_newton)
     d.max_cg = int(max_cg)
     d.k_mode = int(k_mode)
-    d.flags = (FLAG_TANGENT if tangent else 0) | (FLAG_DENSITY if density else 0)
+    d.flags = (FLAG_TANGENT if tangent else 0) | (FLAG_DENSITY if density else 0) | (FLAG_GRAPH if graph else 0)
+    d.batch = int(batch)
     return d
 
 
@@ -183,7 +193,8 @@ class FFTHomog:
         self.c = (3 if self.ndim == 2 else 6) if kinematics == "small" else self.ndim * self.ndim
         self.N = int(np.prod(self.shape))
         self.desc = make_desc(shape, kinematics, material, nphase, **kw)
-        self.batch_max = self.c if kw.get("tangent") else 1
+        self.cells = max(1, int(kw.get("batch", 1)))
+        self.batch_max = self.c * self.cells if kw.get("tangent") else 1
         self.device = torch.device(device if device is not None else "cuda")
         nbytes = fft_homog_workspace_size(self.desc)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -225,8 +236,9 @@ class FFTHomog:
     # ------------------------------------------------------------------ C ABI
     def set_material(self, phase, table, density=None, simp_p=3.0):
         ph = self._dev(phase, self.torch.uint8)
-        assert ph.numel() == self.N
+        assert ph.numel() == self.N * self.cells
         tab = np.ascontiguousarray(table, dtype=np.float64)
+        assert tab.size == 2 * self.desc.nphase * self.cells
         den = None if density is None else self._dev(density, self.torch.float64)
         self._keep = (ph, den)
         rc = self.L.fft_homog_set_material(self.h, _tptr(ph), _dptr(tab),
@@ -245,11 +257,22 @@ class FFTHomog:
         return out, en.value, st.as_dict()
 
     def tangent(self, allow=()):
-        C = np.zeros((self.c, self.c))
+        """(c, c) tangent; (batch, c, c) on a multi-cell handle."""
+        C = np.zeros((self.cells, self.c, self.c))
         st = Stats()
         rc = self.L.fft_homog_tangent(self.h, _dptr(C), ctypes.byref(st))
         self._check(rc, allow)
-        return C, st.as_dict()
+        return (C[0] if self.cells == 1 else C), st.as_dict()
+
+    def launch_shape(self):
+        s = (ctypes.c_int * 6)()
+        self._check(self.L.fft_homog_get_launch_shape(self.h, s))
+        return _shape_dict(s)
+
+    def autotune(self, reps=10):
+        s = (ctypes.c_int * 6)()
+        self._check(self.L.fft_homog_autotune(self.h, int(reps), s))
+        return _shape_dict(s)
 
     def reset(self):
         """Back to the undeformed reference state (eps = 0 / F = I) with zero macro load."""
@@ -356,6 +379,14 @@ def fft_homog_get_field(h, which):
 
 def fft_homog_set_field(h, full, macro):
     return h.set_field(full, macro)
+
+
+def fft_homog_get_launch_shape(h):
+    return h.launch_shape()
+
+
+def fft_homog_autotune(h, reps=10):
+    return h.autotune(reps)
 
 
 def fft_homog_destroy(h):

@@ -10,6 +10,7 @@ constexpr int kMaxStages = 20;
 constexpr int kMaxC = 9;
 constexpr int kMaxAxis = 1024;
 constexpr int kThreads = 256;
+constexpr int kMaxPhase = 256;  // phase-table rows reserved per cell
 
 // Radix schedules compiled into the FFT engine for the common axis lengths; the
 // host factorisation returns the same schedule for these lengths.

@@ -21,7 +21,6 @@ using namespace fh;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxPhase = 256;
 constexpr int kResults = 128;
 constexpr int kChunk = 8;          // CG iterations enqueued between host checks
 constexpr size_t kLdsFft = 48 * 1024;
@@ -55,7 +54,9 @@ bool factorize(int n, int* radix, int* nst) {
 
 struct Layout {
   size_t F, x, r, p, spec, kst, phase, density, scale, table, tw[3], partials, state, results, flags, total;
+  int cells;  // independent cells (microstructures) of this grid held by the handle
   int B, R, TXm, TXo, nblk_x, nblk_vox;
+  size_t n_results;
   int in_x, in_m, in_o;  // in-place (register-staged) FFT per pass
   size_t n_partials, smem_max;
 };
@@ -95,6 +96,17 @@ int validate_desc(const fft_homog_desc* d) {
   if (!(d->tol_newton > 0.0) || !(d->tol_cg > 0.0)) return FFT_HOMOG_EINVAL;
   if (d->max_newton < 0 || d->max_cg < 0) return FFT_HOMOG_EINVAL;
   if (d->k_mode != FFT_HOMOG_K_RECOMPUTE && d->k_mode != FFT_HOMOG_K_STORED) return FFT_HOMOG_EINVAL;
+  if (d->batch < 0) return FFT_HOMOG_EINVAL;
+  if (d->flags & ~(FFT_HOMOG_FLAG_TANGENT | FFT_HOMOG_FLAG_DENSITY | FFT_HOMOG_FLAG_GRAPH)) return FFT_HOMOG_EINVAL;
+  if (d->batch > 1) {
+    // a multi-cell handle runs the tangent solves of every cell at the reference state
+    if (!(d->flags & FFT_HOMOG_FLAG_TANGENT)) return FFT_HOMOG_EINVAL;
+    if (d->flags & FFT_HOMOG_FLAG_DENSITY) return FFT_HOMOG_EINVAL;
+    if (d->k_mode != FFT_HOMOG_K_RECOMPUTE) return FFT_HOMOG_EINVAL;
+    const long long C = ncomp_of(d->kinematics, d->ndim);
+    // grid limits of the batched launches (B * c blocks along z of the spectral passes)
+    if ((long long)d->batch * C * C > 65535) return FFT_HOMOG_EUNSUPPORTED;
+  }
   return FFT_HOMOG_OK;
 }
 
@@ -108,7 +120,8 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
     int rad[kMaxStages], ns;
     if (!factorize(d->n[a], rad, &ns)) return FFT_HOMOG_EUNSUPPORTED;
   }
-  L->B = (d->flags & FFT_HOMOG_FLAG_TANGENT) ? C : 1;
+  L->cells = d->batch > 1 ? d->batch : 1;
+  L->B = (d->flags & FFT_HOMOG_FLAG_TANGENT) ? C * L->cells : 1;
   AxisPlan pl[3];
   for (int a = 0; a < 3; ++a) {
     pl[a].n = a < d->ndim ? d->n[a] : 1;
@@ -179,18 +192,20 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->p = take(fld * L->B);
   L->spec = take((size_t)L->B * C * g.Nh * sizeof(double2));
   L->kst = take(d->k_mode == FFT_HOMOG_K_STORED ? (size_t)C * (C + 1) / 2 * g.N * sizeof(double) : 0);
-  L->phase = take((size_t)g.N);
+  L->phase = take((size_t)L->cells * g.N);
   L->density = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
   L->scale = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
-  L->table = take(2 * kMaxPhase * sizeof(double));
+  L->table = take((size_t)L->cells * 2 * kMaxPhase * sizeof(double));
   for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? (size_t)d->n[a] * sizeof(double2) : 0);
-  size_t np = (size_t)L->B * L->nblk_x;
+  // room for one partial per row, so that any x-pass block height fits (launch-shape tuning)
+  size_t np = (size_t)L->B * rows;
   np = std::max(np, (size_t)C * C * L->nblk_vox);
   np = std::max(np, (size_t)(C + 1) * L->nblk_vox);
   L->n_partials = np;
   L->partials = take(np * sizeof(double));
   L->state = take((size_t)L->B * sizeof(CgState));
-  L->results = take(kResults * sizeof(double));
+  L->n_results = std::max((size_t)kResults, (size_t)L->cells * C * C);
+  L->results = take(L->n_results * sizeof(double));
   L->flags = take(16 * sizeof(int));
   L->total = off;
   return FFT_HOMOG_OK;
@@ -220,6 +235,10 @@ struct fft_homog {
   double* h_results;
   int* h_flags;
   hipEvent_t ev0, ev1;
+  // replayable chunks of CG iterations (FLAG_GRAPH): [0] one right-hand side, [1] the batch
+  hipStream_t cap;
+  hipGraphExec_t gexec[2];
+  int gB[2];
   std::string err;
 };
 
@@ -257,6 +276,7 @@ XFwdArgs xfwd_args(fft_homog_t* h) {
   a.Kst = h->kst;
   a.spec = h->spec;
   a.mat = h->mat;
+  a.per_inst = h->L.cells > 1 ? h->g.c : 0;
   a.st = h->st;
   a.partials = h->partials;
   return a;
@@ -279,22 +299,83 @@ XInvArgs xinv_args(fft_homog_t* h) {
   return a;
 }
 
-AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st) {
+AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inplace = -1) {
   AxisArgs a;
   a.g = h->g;
   a.pl = h->plan[axis];
   a.TX = TX;
-  a.inplace = (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
+  a.inplace = inplace >= 0 ? inplace : (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
   a.spec = h->spec;
   a.st = st;
   return a;
 }
 
 // spectral part shared by every operator application: y, outer (+G-hat), y^-1
+hipError_t enqueue_spectral(fft_homog_t* h, int mode, int B, const CgState* st, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (h->g.ndim == 3 && mode != OUTER_INV) e = launch_mid(-1, axis_args(h, 1, h->L.TXm, st), B, s);
+  if (e == hipSuccess) e = launch_outer(mode, axis_args(h, h->g.ndim - 1, h->L.TXo, st), B, s);
+  if (e == hipSuccess && h->g.ndim == 3 && mode != OUTER_FWD) e = launch_mid(1, axis_args(h, 1, h->L.TXm, st), B, s);
+  return e;
+}
+
 int spectral_middle(fft_homog_t* h, int mode, int B, const CgState* st) {
-  if (h->g.ndim == 3 && mode != OUTER_INV) FH_CK(launch_mid(-1, axis_args(h, 1, h->L.TXm, st), B, h->stream));
-  FH_CK(launch_outer(mode, axis_args(h, h->g.ndim - 1, h->L.TXo, st), B, h->stream));
-  if (h->g.ndim == 3 && mode != OUTER_FWD) FH_CK(launch_mid(1, axis_args(h, 1, h->L.TXm, st), B, h->stream));
+  FH_CK(enqueue_spectral(h, mode, B, st, h->stream));
+  return FFT_HOMOG_OK;
+}
+
+// m CG iterations on every running right-hand side, enqueued on stream s
+hipError_t enqueue_cg_iters(fft_homog_t* h, int B, int m, hipStream_t s) {
+  const int prod = h->desc.k_mode == FFT_HOMOG_K_STORED ? PROD_CGOP_STORED : PROD_CGOP;
+  XFwdArgs a = xfwd_args(h);
+  a.in = h->r;
+  a.p = h->p;
+  XInvArgs ai = xinv_args(h);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < m && e == hipSuccess; ++i) {
+    e = launch_xfwd(prod, h->matcode, a, B, s);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, s);
+    if (e == hipSuccess) e = enqueue_spectral(h, OUTER_PROJECT, B, h->st, s);
+    if (e == hipSuccess) e = launch_xinv(CONS_CGUPD, ai, B, s);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, s);
+  }
+  return e;
+}
+
+void drop_graphs(fft_homog_t* h) {
+  for (int k = 0; k < 2; ++k) {
+    if (h->gexec[k]) hipGraphExecDestroy(h->gexec[k]);
+    h->gexec[k] = nullptr;
+    h->gB[k] = 0;
+  }
+}
+
+// Enqueue m CG iterations.  With FLAG_GRAPH a full chunk is one launch of a graph
+// captured (on a private stream, which the capture does not run) from the same
+// launches; every kernel argument is a workspace pointer or a launch-shape
+// constant, so the graph stays valid until the material or the shape changes.
+int cg_chunk(fft_homog_t* h, int B, int m) {
+  if (!(h->desc.flags & FFT_HOMOG_FLAG_GRAPH) || m != kChunk) {
+    FH_CK(enqueue_cg_iters(h, B, m, h->stream));
+    return FFT_HOMOG_OK;
+  }
+  const int k = B == 1 ? 0 : 1;
+  if (!h->gexec[k] || h->gB[k] != B) {
+    if (h->gexec[k]) hipGraphExecDestroy(h->gexec[k]);
+    h->gexec[k] = nullptr;
+    FH_CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_cg_iters(h, B, kChunk, h->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(h, FFT_HOMOG_EDEVICE, hipGetErrorString(e));
+    h->gexec[k] = ex;
+    h->gB[k] = B;
+  }
+  FH_CK(hipGraphLaunch(h->gexec[k], h->stream));
   return FFT_HOMOG_OK;
 }
 
@@ -334,11 +415,6 @@ int rhs_chain(fft_homog_t* h, int prod, int B, const double* unit) {
 
 // conjugate gradients on all running right-hand sides until none is running
 int cg_loop(fft_homog_t* h, int B) {
-  const int prod = h->desc.k_mode == FFT_HOMOG_K_STORED ? PROD_CGOP_STORED : PROD_CGOP;
-  XFwdArgs a = xfwd_args(h);
-  a.in = h->r;
-  a.p = h->p;
-  XInvArgs ai = xinv_args(h);
   for (;;) {
     bool running = false;
     int done = 1 << 30;
@@ -348,16 +424,10 @@ int cg_loop(fft_homog_t* h, int B) {
         done = std::min(done, h->h_st[b].iters);
       }
     if (!running) return FFT_HOMOG_OK;
-    int m = std::min(kChunk, std::max(1, h->desc.max_cg - done));
-    for (int i = 0; i < m; ++i) {
-      FH_CK(launch_xfwd(prod, h->matcode, a, B, h->stream));
-      FH_CK(launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, h->stream));
-      int rc = spectral_middle(h, OUTER_PROJECT, B, h->st);
-      if (rc) return rc;
-      FH_CK(launch_xinv(CONS_CGUPD, ai, B, h->stream));
-      FH_CK(launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, h->stream));
-    }
-    int rc = read_states(h, B);
+    const int m = std::min(kChunk, std::max(1, h->desc.max_cg - done));
+    int rc = cg_chunk(h, B, m);
+    if (rc) return rc;
+    rc = read_states(h, B);
     if (rc) return rc;
     bool still = false;
     for (int b = 0; b < B; ++b) still = still || h->h_st[b].status == CG_RUNNING;
@@ -394,6 +464,20 @@ int reduce_to_host(fft_homog_t* h, int nslots, int nblocks) {
   FH_CK(hipMemcpyAsync(h->h_results, h->results, nslots * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   FH_CK(hipStreamSynchronize(h->stream));
   return FFT_HOMOG_OK;
+}
+
+// Average device time (ms) of `reps` launches of `body` after one untimed launch.
+template <class Body>
+hipError_t time_launches(fft_homog_t* h, int reps, Body body, double* ms) {
+  hipError_t e = body();
+  if (e == hipSuccess) e = hipEventRecord(h->ev0, h->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = body();
+  if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, h->ev0, h->ev1);
+  *ms = (double)t / reps;
+  return e;
 }
 
 }  // namespace
@@ -453,17 +537,24 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   h->simp_p = 0.0;
   h->h_st = nullptr;
   h->ev0 = h->ev1 = nullptr;
+  h->cap = nullptr;
+  h->gexec[0] = h->gexec[1] = nullptr;
+  h->gB[0] = h->gB[1] = 0;
 
-  hipError_t e = hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + kResults * sizeof(double) + 64, 0);
+  hipError_t e = hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + L.n_results * sizeof(double) + 64, 0);
   if (e != hipSuccess) {
     delete h;
     return create_fail(FFT_HOMOG_EDEVICE, "hipHostMalloc", e);
   }
   h->h_results = (double*)((char*)h->h_st + L.B * sizeof(CgState));
-  h->h_flags = (int*)(h->h_results + kResults);
+  h->h_flags = (int*)(h->h_results + L.n_results);
   const char* step = "hipEventCreate";
   e = hipEventCreate(&h->ev0);
   if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+  if (e == hipSuccess && (d->flags & FFT_HOMOG_FLAG_GRAPH)) {
+    step = "capture stream";
+    e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+  }
 
   // twiddle tables, computed in extended precision and rounded once
   std::vector<double2> tw[3];
@@ -483,14 +574,14 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
     e = hipMemcpyAsync(dtw, tw[a].data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream);
   }
   if (h->g.ndim == 2) h->plan[2] = h->plan[1];
-  std::vector<double> zeros(2 * kMaxPhase, 0.0);
+  std::vector<double> zeros((size_t)L.cells * 2 * kMaxPhase, 0.0);
   if (e == hipSuccess) {
     step = "phase table init";
     e = hipMemcpyAsync(h->table, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   }
   if (e == hipSuccess) {
     step = "phase map init";
-    e = hipMemsetAsync(h->phase, 0, (size_t)h->g.N, h->stream);
+    e = hipMemsetAsync(h->phase, 0, (size_t)L.cells * h->g.N, h->stream);
   }
   if (e == hipSuccess) {
     step = "reference strain";
@@ -517,10 +608,14 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
                            double simp_p) {
   if (!h || !phase || !lm) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   if (density && !h->density) return fail(h, FFT_HOMOG_EINVAL, "density given but FLAG_DENSITY not set");
-  for (int k = 0; k < 2 * h->desc.nphase; ++k)
+  const int cells = h->L.cells;
+  const size_t row = 2 * (size_t)h->desc.nphase * sizeof(double);
+  for (long long k = 0; k < 2LL * h->desc.nphase * cells; ++k)
     if (!std::isfinite(lm[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite phase table entry");
-  FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)h->g.N, hipMemcpyDeviceToDevice, h->stream));
-  FH_CK(hipMemcpyAsync(h->table, lm, 2 * h->desc.nphase * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  drop_graphs(h);
+  FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)cells * h->g.N, hipMemcpyDeviceToDevice, h->stream));
+  FH_CK(hipMemcpy2DAsync(h->table, 2 * kMaxPhase * sizeof(double), lm, row, row, cells, hipMemcpyHostToDevice,
+                         h->stream));
   if (density) {
     FH_CK(hipMemcpyAsync(h->density, density, (size_t)h->g.N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     FH_CK(launch_simp_scale(h->density, simp_p, h->scale, h->g.N, h->stream));
@@ -529,7 +624,7 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
   h->simp_p = simp_p;
   h->h_flags[0] = 0;
   FH_CK(hipMemcpyAsync(h->flags, h->h_flags, sizeof(int), hipMemcpyHostToDevice, h->stream));
-  FH_CK(launch_check_phase(h->phase, h->g.N, h->desc.nphase, h->flags, h->stream));
+  FH_CK(launch_check_phase(h->phase, (long long)cells * h->g.N, h->desc.nphase, h->flags, h->stream));
   FH_CK(hipMemcpyAsync(h->h_flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   FH_CK(hipStreamSynchronize(h->stream));
   h->solved_ok = false;
@@ -540,6 +635,7 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
 int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, double* macro_stress, double* energy,
                     fft_homog_stats* stats) {
   if (!h || !macro || n_increments < 1) return fail(h, FFT_HOMOG_EINVAL, "bad solve arguments");
+  if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
   const int C = h->g.c;
   for (int k = 0; k < C; ++k)
     if (!std::isfinite(macro[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite macro load");
@@ -623,30 +719,42 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
 int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
   if (!h || !Cout) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   if (!(h->desc.flags & FFT_HOMOG_FLAG_TANGENT)) return fail(h, FFT_HOMOG_ESTATE, "FLAG_TANGENT not set at create");
-  if (!h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
+  const int cells = h->L.cells;
+  // a multi-cell handle never leaves the reference state
+  if (cells == 1 && !h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
   const int C = h->g.c;
+  const int B = h->L.B;
   fft_homog_stats S;
   memset(&S, 0, sizeof(S));
   FH_CK(hipEventRecord(h->ev0, h->stream));
   double unit[kMaxC];
   unit_loads(h, unit);
-  int rc = rhs_chain(h, PROD_TRHS, C, unit);
+  int rc = rhs_chain(h, PROD_TRHS, B, unit);
   if (rc) return rc;
   if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
-  rc = cg_loop(h, C);
+  rc = cg_loop(h, B);
   if (rc) return rc;
   int status = FFT_HOMOG_OK;
-  for (int b = 0; b < C; ++b) {
+  for (int b = 0; b < B; ++b) {
     const CgState& s = h->h_st[b];
     S.cg_iterations += s.iters;
     if (S.n_recorded < FFT_HOMOG_MAX_RECORDED) S.cg_per_newton[S.n_recorded++] = s.iters;
     if (s.status == CG_BREAKDOWN) status = FFT_HOMOG_EBREAKDOWN;
     else if (s.status == CG_MAXIT && status == FFT_HOMOG_OK) status = FFT_HOMOG_ENOTCONV;
   }
-  FH_CK(launch_tangent_matrix(h->matcode, h->F, h->x, unit, h->mat, h->partials, h->L.nblk_vox, h->g, h->stream));
-  rc = reduce_to_host(h, C * C, h->L.nblk_vox);
-  if (rc) return rc;
-  for (int k = 0; k < C * C; ++k) Cout[k] = h->h_results[k] / (double)h->g.N;
+  // C_IJ of each cell: the partial sums of one cell are reduced before the next reuses them
+  for (int cell = 0; cell < cells; ++cell) {
+    MatParams m = h->mat;
+    m.phase += (long long)cell * h->g.N;
+    m.table += (long long)cell * 2 * kMaxPhase;
+    const double* X = h->x + (size_t)cell * C * C * h->g.N;
+    FH_CK(launch_tangent_matrix(h->matcode, h->F, X, unit, m, h->partials, h->L.nblk_vox, h->g, h->stream));
+    FH_CK(launch_reduce_slots(h->partials, C * C, h->L.nblk_vox, h->results + (size_t)cell * C * C, h->stream));
+  }
+  FH_CK(hipMemcpyAsync(h->h_results, h->results, (size_t)cells * C * C * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  for (long long k = 0; k < (long long)cells * C * C; ++k) Cout[k] = h->h_results[k] / (double)h->g.N;
   FH_CK(hipEventRecord(h->ev1, h->stream));
   FH_CK(hipEventSynchronize(h->ev1));
   float ms = 0.f;
@@ -660,6 +768,7 @@ int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
 int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, double* grad_density,
                       fft_homog_stats* stats) {
   if (!h || !w_stress || !grad_density) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
   if (!h->mat.scale) return fail(h, FFT_HOMOG_ESTATE, "no density field set (FLAG_DENSITY and set_material)");
   if (!h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
   if (!std::isfinite(w_energy)) return fail(h, FFT_HOMOG_EINVAL, "non-finite weight");
@@ -711,6 +820,7 @@ int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, d
 
 int fft_homog_get_field(fft_homog_t* h, int which, double* dst) {
   if (!h || !dst) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
   if (which == FFT_HOMOG_FIELD_STRAIN) {
     FH_CK(launch_expand(h->F, dst, h->g, h->stream));
   } else if (which == FFT_HOMOG_FIELD_STRESS) {
@@ -727,6 +837,7 @@ int fft_homog_get_field(fft_homog_t* h, int which, double* dst) {
 
 int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro) {
   if (!h || !src || !macro) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
   FH_CK(launch_pack(src, h->F, h->g, h->stream));
   to_packed(h, macro, h->macro_cur);
   FH_CK(hipStreamSynchronize(h->stream));
@@ -741,6 +852,8 @@ void fft_homog_destroy(fft_homog_t* h) {
   if (h->h_st) hipHostFree(h->h_st);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  drop_graphs(h);
+  if (h->cap) hipStreamDestroy(h->cap);
   delete h;
 }
 
@@ -902,6 +1015,127 @@ int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
   if (h->h_st[0].status != CG_RUNNING && h->h_st[0].status != CG_MAXIT)
     return fail(h, FFT_HOMOG_ESTATE, "timed CG stopped early (breakdown)");
   for (int k = 0; k < 7; ++k) ms[k] = acc[k] / iters;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[6]) {
+  if (!h || !shape) return FFT_HOMOG_EINVAL;
+  shape[0] = h->L.R;
+  shape[1] = h->L.TXm;
+  shape[2] = h->L.TXo;
+  shape[3] = h->L.in_x;
+  shape[4] = h->L.in_m;
+  shape[5] = h->L.in_o;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
+  if (!h || reps < 1) return fail(h, FFT_HOMOG_EINVAL, "bad arguments");
+  const Geom& g = h->g;
+  const int C = g.c;
+  const int B = h->L.B;
+  const int rows = g.ny * g.nz;
+  const AxisPlan& pouter = h->plan[g.ndim - 1];
+  // A candidate replaces the incumbent only when it is clearly faster, so that timing
+  // noise does not move the shape away from the default.
+  const double kGain = 0.98;
+  // candidates stay within the default per-block LDS limit (more would cut the blocks
+  // per CU to two or one); the incumbent is always timed
+  const size_t kLdsTune = 64 * 1024;
+  drop_graphs(h);
+  // work vectors at zero, every right-hand side running with alpha = beta = 0: the passes
+  // then do all their loads, stores and arithmetic while the state stays put (no reduction
+  // runs, so nothing can stop the solve)
+  const size_t vec = (size_t)B * C * g.N * sizeof(double);
+  FH_CK(hipMemsetAsync(h->x, 0, vec, h->stream));
+  FH_CK(hipMemsetAsync(h->r, 0, vec, h->stream));
+  FH_CK(hipMemsetAsync(h->p, 0, vec, h->stream));
+  int rc = upload_states(h, B);
+  if (rc) return rc;
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, g, h->stream));
+  const int prod = h->kst ? PROD_CGOP_STORED : PROD_CGOP;
+
+  // x passes: block height and register staging (forward and inverse together)
+  {
+    int best_r = h->L.R, best_ip = h->L.in_x;
+    double best = 0.0;
+    const int rmax = std::min(16, rows);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int r = rmax; r >= 1; --r)
+        for (int ip = 1; ip >= 0; --ip) {
+          const bool incumbent = (r == h->L.R && ip == h->L.in_x);
+          if ((pass == 0) != incumbent) continue;  // time the incumbent first
+          if (ip && !inplace_ok(h->plan[0], (C * r + 1) / 2)) continue;
+          if (!incumbent && std::max(xfwd_smem(g, r, ip), xinv_smem(g, r, ip)) > kLdsTune) continue;
+          XFwdArgs a = xfwd_args(h);
+          a.in = h->r;
+          a.p = h->p;
+          a.R = r;
+          a.nblocks = (rows + r - 1) / r;
+          a.inplace = ip;
+          XInvArgs ai = xinv_args(h);
+          ai.R = r;
+          ai.nblocks = a.nblocks;
+          ai.inplace = ip;
+          double ms = 0.0;
+          FH_CK(time_launches(h, reps, [&]() {
+            hipError_t e = launch_xfwd(prod, h->matcode, a, B, h->stream);
+            return e == hipSuccess ? launch_xinv(CONS_CGUPD, ai, B, h->stream) : e;
+          }, &ms));
+          if (incumbent) best = ms;
+          else if (ms < kGain * best) { best = ms; best_r = r; best_ip = ip; }
+        }
+    h->L.R = best_r;
+    h->L.in_x = best_ip;
+    h->L.nblk_x = (rows + best_r - 1) / best_r;
+  }
+  // y passes (3D): kx bins per block, forward and inverse together
+  if (g.ndim == 3) {
+    int best_t = h->L.TXm, best_ip = h->L.in_m;
+    double best = 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int t = std::min(16, g.nxh); t >= 1; --t)
+        for (int ip = 1; ip >= 0; --ip) {
+          const bool incumbent = (t == h->L.TXm && ip == h->L.in_m);
+          if ((pass == 0) != incumbent) continue;
+          if (ip && !inplace_ok(h->plan[1], t)) continue;
+          if (!incumbent && mid_smem(g, t, ip) > kLdsTune) continue;
+          const AxisArgs a = axis_args(h, 1, t, h->st, ip);
+          double ms = 0.0;
+          FH_CK(time_launches(h, reps, [&]() {
+            hipError_t e = launch_mid(-1, a, B, h->stream);
+            return e == hipSuccess ? launch_mid(1, a, B, h->stream) : e;
+          }, &ms));
+          if (incumbent) best = ms;
+          else if (ms < kGain * best) { best = ms; best_t = t; best_ip = ip; }
+        }
+    h->L.TXm = best_t;
+    h->L.in_m = best_ip;
+  }
+  // outer pass: kx bins per block
+  {
+    const int G = outer_group(g);
+    int best_t = h->L.TXo, best_ip = h->L.in_o;
+    double best = 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int t = std::min(8, g.nxh); t >= 1; --t)
+        for (int ip = 1; ip >= 0; --ip) {
+          const bool incumbent = (t == h->L.TXo && ip == h->L.in_o);
+          if ((pass == 0) != incumbent) continue;
+          if (ip && !inplace_ok(pouter, G * t)) continue;
+          if (!incumbent && outer_smem(g, t, ip) > kLdsTune) continue;
+          const AxisArgs a = axis_args(h, g.ndim - 1, t, h->st, ip);
+          double ms = 0.0;
+          FH_CK(time_launches(h, reps, [&]() { return launch_outer(OUTER_PROJECT, a, B, h->stream); }, &ms));
+          if (incumbent) best = ms;
+          else if (ms < kGain * best) { best = ms; best_t = t; best_ip = ip; }
+        }
+    h->L.TXo = best_t;
+    h->L.in_o = best_ip;
+  }
+  h->L.smem_max = std::max(std::max(xfwd_smem(g, h->L.R, h->L.in_x), xinv_smem(g, h->L.R, h->L.in_x)),
+                           std::max(mid_smem(g, h->L.TXm, h->L.in_m), outer_smem(g, h->L.TXo, h->L.in_o)));
+  if (shape) fft_homog_get_launch_shape(h, shape);
   return FFT_HOMOG_OK;
 }
 

@@ -23,10 +23,11 @@ struct XFwdArgs {
   const double* F;       // linearisation point / strain [c][N]
   const double* Kst;     // stored tangent [c(c+1)/2][N]
   double2* spec;         // [B][c][Nh]
-  MatParams mat;
+  MatParams mat;          // cell 0; cell i has its phase map at phase + i N, its table at table + i 2 kMaxPhase
+  int per_inst;          // right-hand sides per cell of a multi-cell batch (0: one cell, every b uses cell 0)
   CgState* st;           // per right-hand side
   double* partials;      // [B][nblocks]
-  double unit[kMaxC];    // TRHS: unit load b is unit[b] * e_b in the packed basis; ADJ: packed W
+  double unit[kMaxC];    // TRHS: load l of a cell is unit[l] * e_l in the packed basis; ADJ: packed W
   double w_energy;       // ADJ: weight of the energy in the objective
 };
 

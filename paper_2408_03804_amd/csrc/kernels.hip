@@ -98,6 +98,15 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
     if (a.st[b].status != CG_RUNNING) return;
   }
   const Geom& g = a.g;
+  // cell of this right-hand side and its load index within the cell
+  MatParams mat = a.mat;
+  int lb = b;
+  if (a.per_inst > 0) {
+    const int cell = b / a.per_inst;
+    lb = b - cell * a.per_inst;
+    mat.phase += (long long)cell * g.N;
+    mat.table += (long long)cell * 2 * kMaxPhase;
+  }
   const int nx = g.nx;
   const int rows = g.ny * g.nz;
   const int row0 = blockIdx.x * a.R;
@@ -143,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       }
       {
         double lam, mu;
-        load_lame(a.mat, vox, lam, mu);  // brings the phase id and table line into cache
+        load_lame(mat, vox, lam, mu);  // brings the phase id and table line into cache
         (void)lam;
         (void)mu;
       }
@@ -182,7 +191,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       // so the tangent passes do not read it
       // (lam, mu) are re-read here (cache hits): staging them in LDS as well
       // raises the register count of the fused kernel by a third
-      load_lame(a.mat, vox, lam, mu);
+      load_lame(mat, vox, lam, mu);
       if (CGOP) {
 #pragma unroll
         for (int j = 0; j < C; ++j) e[j] = (PROD == PROD_CGOP && MAT != MAT_LE) ? E[j * nv + t] : 0.0;
@@ -216,7 +225,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       } else if (PROD == PROD_TRHS) {
         double de[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) de[j] = (j == b) ? a.unit[b] : 0.0;
+        for (int j = 0; j < C; ++j) de[j] = (j == lb) ? a.unit[lb] : 0.0;
         tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) acc += v[j] * v[j];

@@ -171,3 +171,28 @@ def workload_neohookean3d(n=128, seed=0, correlation_length=8.0):
                 material="neo_hookean",
                 phase=grf_two_phase((n, n, n), correlation_length, 0.30, seed),
                 table=table, macro=F.reshape(-1), n_increments=10)
+
+
+def workload_uq_cells(n_cells=256, sizes=(32, 48, 64, 96), seed=0, stiff_ratio=10.0):
+    """Many small-strain linear elastic cells of uneven size (uncertainty quantification).
+
+    Per cell, from one seeded stream: edge n uniform over ``sizes``; a thresholded
+    Gaussian random field with correlation length ~ U[4, 12] voxels and stiff
+    fraction ~ U[0.1, 0.5]; matrix Young's modulus ~ lognormal(0, 0.2); the stiff
+    phase ``stiff_ratio`` times stiffer; nu = 0.3 in both.  The stiff modulus is
+    not fixed by the workload statement; 10 x the matrix is the reading used.
+    Returns a list of dicts with keys shape, phase, table, seed.
+    """
+    rng = np.random.default_rng(seed)
+    cells = []
+    for i in range(n_cells):
+        n = int(sizes[int(rng.integers(0, len(sizes)))])
+        ell = float(rng.uniform(4.0, 12.0))
+        frac = float(rng.uniform(0.1, 0.5))
+        E0 = float(rng.lognormal(0.0, 0.2))
+        cell_seed = int(rng.integers(0, 2 ** 31 - 1))
+        phase = grf_two_phase((n, n, n), ell, frac, cell_seed)
+        table = np.array([lame(E0, 0.3), lame(stiff_ratio * E0, 0.3)])
+        cells.append(dict(shape=(n, n, n), phase=phase, table=table, seed=cell_seed,
+                          correlation_length=ell, stiff_fraction=frac))
+    return cells

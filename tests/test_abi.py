@@ -36,8 +36,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # int ndim; int n[3]; double len[3]; 4 ints; 2 doubles; 3 ints; unsigned -> natural alignment
-    assert ctypes.sizeof(binding.Desc) == 4 + 12 + 24 + 16 + 16 + 16
+    # int ndim; int n[3]; double len[3]; 3 ints + pad; 2 doubles; 3 ints; unsigned; int batch + pad
+    assert ctypes.sizeof(binding.Desc) == 4 + 12 + 24 + 16 + 16 + 16 + 8
+    assert binding.Desc.batch.offset == 88
     assert ctypes.sizeof(binding.Stats) == 16 + 24 + 8 + 4 * binding.MAX_RECORDED
 
 
@@ -63,6 +64,12 @@ def test_workspace_size_is_host_only_and_sane(shape, kin, mat):
     (lambda d: setattr(d, "nphase", 0), "einval"),
     (lambda d: setattr(d, "material", 1), "einval"),   # Neo-Hookean with small strain
     (lambda d: d.n.__setitem__(1, 4096), "eunsupported"),
+    (lambda d: setattr(d, "flags", 8), "einval"),                     # unknown flag
+    (lambda d: setattr(d, "batch", -1), "einval"),
+    (lambda d: setattr(d, "batch", 4), "einval"),                     # multi-cell without FLAG_TANGENT
+    (lambda d: (setattr(d, "batch", 4), setattr(d, "flags", 3)), "einval"),   # ... with FLAG_DENSITY
+    (lambda d: (setattr(d, "batch", 4), setattr(d, "flags", 1), setattr(d, "k_mode", 1)), "einval"),
+    (lambda d: (setattr(d, "batch", 2000), setattr(d, "flags", 1)), "eunsupported"),  # 2000 * 36 blocks
 ])
 def test_invalid_descriptors_rejected_on_host(mutate, code):
     d = binding.make_desc((8, 8, 8), "small", "linear_elastic", 2)
@@ -70,6 +77,17 @@ def test_invalid_descriptors_rejected_on_host(mutate, code):
     with pytest.raises(binding.FFTHomogError) as ei:
         binding.fft_homog_workspace_size(d)
     assert ei.value.status == code
+
+
+def test_multi_cell_workspace_scales_with_cells():
+    one = binding.fft_homog_workspace_size(binding.make_desc((16, 16, 16), "small", "linear_elastic", 2,
+                                                             tangent=True))
+    many = binding.fft_homog_workspace_size(binding.make_desc((16, 16, 16), "small", "linear_elastic", 2,
+                                                              tangent=True, batch=8))
+    c, N = 6, 16 ** 3
+    # x, r, p and the half spectrum of 6 right-hand sides per cell grow; F stays shared
+    assert many - one >= 7 * 6 * c * N * 8 * 3
+    assert many < 8 * one
 
 
 def test_strerror_names_every_status():

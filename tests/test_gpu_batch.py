@@ -1,0 +1,181 @@
+"""Multi-cell tangent solves, HIP-graph replay of the CG iterations and the launch-shape autotuner.
+
+A multi-cell handle runs the ncomp unit-load tangent solves of many cells in the
+same launches.  Each cell's tangent is checked against the oracle's implicit
+tangent at the reference state (same seeded phase map and table), and against
+a one-cell handle running the same cell, which must give the same bits: the
+right-hand sides of different cells never mix (per-right-hand-side CG scalars,
+fixed-order partial sums).  Graph replay must give the bits of direct launches,
+over many replays with host reads in between.  Autotuned launch shapes must keep
+oracle parity.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import lame_fields
+from oracle import closed_forms, newton_cg
+from paper_2408_03804_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_HOMOG = 1e-11
+
+
+def make(shape, kin, mat, nphase=2, **kw):
+    from paper_2408_03804_amd.binding import FFTHomog
+    return FFTHomog(shape, kin, mat, nphase, **kw)
+
+
+def random_cells(shape, k, seed, contrast=20.0):
+    rng = np.random.default_rng(seed)
+    cells = []
+    for i in range(k):
+        phase = workloads.grf_two_phase(shape, float(rng.uniform(1.0, 2.5)), float(rng.uniform(0.2, 0.5)),
+                                        int(rng.integers(0, 1 << 30)))
+        E0 = float(rng.lognormal(0.0, 0.2))
+        table = np.array([workloads.lame(E0, 0.3), workloads.lame(contrast * E0, float(rng.uniform(0.2, 0.35)))])
+        cells.append((phase, table))
+    return cells
+
+
+def oracle_tangent(shape, kin, mat, phase, table, tol_cg=1e-12):
+    lam, mu = lame_fields(phase, table)
+    prob = newton_cg.Problem(shape, mat, lam, mu)
+    C, _, counts = newton_cg.homogenized_tangent(prob, newton_cg.initial_state(prob), tol_cg=tol_cg)
+    return C, counts
+
+
+def one_cell_tangent(shape, kin, mat, phase, table, **kw):
+    h = make(shape, kin, mat, tangent=True, **kw)
+    h.set_material(phase, table)
+    h.solve(np.eye(len(shape)).reshape(-1) if kin == "finite" else np.zeros(h.c), 1)
+    return h.tangent()
+
+
+@pytest.mark.parametrize("shape,kin,mat,k", [((6, 5, 7), "small", "linear_elastic", 3),
+                                             ((7, 9), "small", "linear_elastic", 5),
+                                             ((5, 6, 4), "finite", "neo_hookean", 2),
+                                             ((9, 6), "finite", "stvk", 3)])
+def test_multi_cell_tangent_matches_oracle_per_cell(shape, kin, mat, k):
+    cells = random_cells(shape, k, 11)
+    h = make(shape, kin, mat, tangent=True, batch=k, tol_cg=1e-12)
+    h.set_material(np.stack([c[0] for c in cells]), np.stack([c[1] for c in cells]))
+    C, st = h.tangent()
+    assert st["status"] == "ok" and C.shape == (k, h.c, h.c)
+    assert len(st["cg"]) == k * h.c
+    for i, (phase, table) in enumerate(cells):
+        Cref, counts = oracle_tangent(shape, kin, mat, phase, table)
+        scale = np.abs(Cref).max()
+        assert np.abs(C[i] - Cref).max() < TOL_HOMOG * scale, i
+        assert np.abs(C[i] - C[i].T).max() < 1e-12 * scale
+        # at tol 1e-12 the last iterations sit at the rounding floor of the residual
+        # recurrence, where <p, K:p> (GPU) and <p, G(K:p)> (oracle) round differently
+        for a, b in zip(st["cg"][i * h.c:(i + 1) * h.c], counts):
+            assert abs(a - b) <= max(1, 0.05 * b)
+
+
+def test_multi_cell_equals_one_cell_handles_bitwise():
+    shape = (12, 10, 8)
+    cells = random_cells(shape, 4, 12)
+    h = make(shape, "small", "linear_elastic", tangent=True, batch=4)
+    h.set_material(np.stack([c[0] for c in cells]), np.stack([c[1] for c in cells]))
+    C, st = h.tangent()
+    for i, (phase, table) in enumerate(cells):
+        Ci, sti = one_cell_tangent(shape, "small", "linear_elastic", phase, table)
+        assert np.array_equal(C[i], Ci), i
+        assert st["cg"][i * 6:(i + 1) * 6] == sti["cg"]
+
+
+def test_homogeneous_cell_inside_a_batch_is_exact():
+    shape = (8, 6, 10)
+    cells = random_cells(shape, 3, 13)
+    hom = (np.zeros(shape, np.uint8), np.array([[1.3, 0.7], [1.3, 0.7]]))
+    cells.insert(1, hom)
+    h = make(shape, "small", "linear_elastic", tangent=True, batch=4)
+    h.set_material(np.stack([c[0] for c in cells]), np.stack([c[1] for c in cells]))
+    C, st = h.tangent()
+    assert st["cg"][6:12] == [0] * 6
+    Cm = closed_forms.isotropic_matrix(1.3, 0.7, 3)
+    assert np.abs(C[1] - Cm).max() < 1e-14 * np.abs(Cm).max()
+    assert all(n > 0 for n in st["cg"][:6])
+
+
+def test_multi_cell_handle_refuses_the_single_cell_calls():
+    from paper_2408_03804_amd.binding import FFTHomogError
+    shape = (4, 4, 4)
+    h = make(shape, "small", "linear_elastic", tangent=True, batch=2)
+    for call in (lambda: h.solve(np.zeros(6), 1), lambda: h.get_field(0),
+                 lambda: h.set_field(np.zeros((9,) + shape), np.zeros(6))):
+        with pytest.raises(FFTHomogError) as ei:
+            call()
+        assert ei.value.status == "eunsupported"
+
+
+def test_graph_replay_is_bitwise_equal_to_direct_launches():
+    w = workloads.workload_neohookean3d(n=16, correlation_length=3.0)
+    outs = []
+    for graph in (False, True, True):
+        h = make(w["shape"], "finite", "neo_hookean", tangent=True, graph=graph)
+        h.set_material(w["phase"], w["table"])
+        S, psi, st = h.solve(w["macro"], 2)
+        # several chunks per linear solve: the graph is replayed many times
+        assert st["status"] == "ok" and max(st["cg"]) > 16
+        C, stc = h.tangent()
+        # a second material on the same handle drops and rebuilds the graph
+        h.set_material(w["phase"], w["table"][::-1].copy())
+        h.reset()
+        S2, _, st2 = h.solve(w["macro"], 1)
+        outs.append((S, psi, st["cg"], h.get_field(0).cpu().numpy(), C, stc["cg"], S2, st2["cg"]))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("shape,kin,mat", [((24, 20, 16), "finite", "neo_hookean"),
+                                           ((33, 28), "small", "linear_elastic")])
+def test_autotuned_shape_keeps_oracle_parity(shape, kin, mat):
+    d = len(shape)
+    phase = workloads.grf_two_phase(shape, 3.0, 0.3, 5)
+    table = np.array([[2.0, 1.0], [40.0, 20.0]]) if kin == "finite" else np.array(
+        [workloads.lame(1.0, 0.3), workloads.lame(10.0, 0.3)])
+    macro = np.diag([1.02] + [1.0] * (d - 1)).reshape(-1) if kin == "finite" else np.r_[0.01, np.zeros(
+        3 if d == 3 else 2)][:3 if d == 2 else 6]
+    h = make(shape, kin, mat, tangent=True, tol_cg=1e-12)
+    h.set_material(phase, table)
+    default = h.launch_shape()
+    tuned = h.autotune(reps=3)
+    assert tuned == h.launch_shape()
+    assert 1 <= tuned["x_rows"] <= 16 and 1 <= tuned["outer_bins"] <= 8
+    if d == 2:
+        assert tuned["y_bins"] == default["y_bins"]
+    S, psi, st = h.solve(macro, 2)
+    assert st["status"] == "ok"
+    lam, mu = lame_fields(phase, table)
+    prob = newton_cg.Problem(shape, mat, lam, mu)
+    ref = newton_cg.solve(prob, macro, n_increments=2, tol_cg=1e-12)
+    Sref = newton_cg.tensor_to_components(newton_cg.homogenized(prob.stress(ref["state"].field)), kin, d)
+    assert np.abs(S - Sref).max() < TOL_HOMOG * np.abs(Sref).max()
+    C, _ = h.tangent()
+    Cref, _, _ = newton_cg.homogenized_tangent(prob, ref["state"], tol_cg=1e-12)
+    assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
+
+
+def test_batcher_groups_uneven_sizes():
+    from paper_2408_03804_amd.batch import TangentBatcher
+    cells = []
+    for shape, k, seed in (((8, 8, 8), 3, 21), ((12, 10, 6), 2, 22), ((8, 8, 8), 2, 23)):
+        cells += [dict(phase=p, table=t) for p, t in random_cells(shape, k, seed)]
+    # a budget of about two 8^3 cells forces several chunks per group
+    from paper_2408_03804_amd import binding
+    two = binding.fft_homog_workspace_size(binding.make_desc((8, 8, 8), "small", "linear_elastic", 2, tangent=True,
+                                                             batch=2))
+    b = TangentBatcher(max_bytes=two, autotune=True)
+    C, info = b.tangents(cells)
+    assert C.shape == (7, 6, 6)
+    assert sum(r["cells"] for r in info) == 7 and max(r["cells"] for r in info) <= 2
+    for i, cell in enumerate(cells):
+        shape = cell["phase"].shape
+        Ci, _ = one_cell_tangent(shape, "small", "linear_elastic", cell["phase"], cell["table"], tol_cg=1e-10)
+        assert np.abs(C[i] - Ci).max() < 1e-9 * np.abs(Ci).max(), i
+    b.close()

@@ -10,6 +10,12 @@ Prints one JSON line (rank 0, one GPU) with a ``roofline`` entry for the
 dominant kernel of the CG iteration (algorithmic bytes / average launch time,
 HIP events on the library's stream) and a ``cpu_baseline`` entry (the CPU
 oracle timed on a bounded sample of CG iterations of the same workload).
+
+``--workload uq256`` / ``tangents32`` instead time homogenized tangents/s of many
+small-strain cells (256 cells of edge 32..96, or 1024 cells of 32^3) through
+multi-cell handles; one step = the 6x6 tangents of every cell, phase maps
+resident in HBM.  Their ``roofline`` is the whole job's effective bandwidth
+(algorithmic bytes of all CG iterations / wall time).
 """
 
 import argparse
@@ -99,6 +105,95 @@ def cpu_oracle_sample(w, iters):
                       "first load increment of the same %s workload, single thread, %.1f s" % (k, w["name"], t1 - t0)}
 
 
+def cpu_tangent_sample(cells, budget_s):
+    """Tangents/s of the CPU oracle (implicit tangent at the reference state) on the first cells, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import newton_cg
+
+    done, t = 0, 0.0
+    with threadpool_limits(limits=1):
+        for cell in cells:
+            tab = np.asarray(cell["table"])
+            prob = newton_cg.Problem(cell["shape"], "linear_elastic", tab[cell["phase"], 0], tab[cell["phase"], 1])
+            t0 = time.perf_counter()
+            newton_cg.homogenized_tangent(prob, newton_cg.initial_state(prob), tol_cg=1e-10)
+            t += time.perf_counter() - t0
+            done += 1
+            if t >= budget_s:
+                break
+    return {"value": done / t, "unit": "tangents/s", "cores": 1, "kind": "oracle",
+            "sample": "implicit 6x6 tangent (6 textbook CG solves, tol 1e-10) of the first %d cell(s) of "
+                      "shape %s of the same workload, single thread, %.1f s" % (done, cells[0]["shape"], t)}
+
+
+def bench_cells(args, name, cells, description):
+    """Homogenized tangents/s of many linear elastic cells through multi-cell handles."""
+    import torch
+
+    from paper_2408_03804_amd.batch import TangentBatcher
+
+    dev = [dict(phase=torch.as_tensor(c["phase"]).to("cuda:0"), table=c["table"]) for c in cells]
+    b = TangentBatcher(tol_cg=1e-10, max_cg=20000, graph=not args.no_graph, autotune=not args.no_autotune,
+                       max_bytes=int(args.max_gb * (1 << 30)), device="cuda:0")
+    for i in range(args.warmup):
+        C, info = b.tangents(dev)
+        log("warmup %d: %s" % (i, ", ".join("%s x%d cg %d %.3fs" % (r["shape"][0], r["cells"], r["cg_total"],
+                                                                   r["seconds"]) for r in info)))
+    for key, shp in b.shapes.items():
+        log("launch shape %s: %s" % (key, shp))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vox_iters = 0
+    cg = 0
+    for i in range(args.steps):
+        C, info = b.tangents(dev)
+        for r in info:
+            if r["status"] != "ok":
+                raise RuntimeError("tangent solve failed: %s" % r)
+            vox_iters += int(np.prod(r["shape"])) * r["cg_total"]
+            cg += r["cg_total"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # whole-job effective bandwidth: algorithmic bytes of every CG iteration run / wall time
+    groups = {}
+    for r in info:
+        groups.setdefault(r["shape"], []).append(r)
+    alg = 0.0
+    for shape, rs in groups.items():
+        n = shape[0]
+        N = n ** 3
+        Nh = (n // 2 + 1) * n * n
+        bpv = sum(algorithmic_bytes_per_voxel(6, N, Nh, False).values())
+        alg += bpv * N * sum(r["cg_total"] for r in rs)
+    alg *= args.steps
+    eff = alg / wall / 1e9
+    cpu = None
+    if not args.no_cpu:
+        small = sorted(cells, key=lambda c: c["phase"].size)
+        cpu = cpu_tangent_sample(small, args.cpu_seconds)
+        log("cpu oracle: %.3e tangents/s" % cpu["value"])
+    out = {
+        "metric": "homogenized 6x6 tangents/s (FP64 Fourier-Galerkin CG, %s)" % name,
+        "value": len(cells) * args.steps / wall,
+        "unit": "tangents/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": description, "cells": len(cells),
+                   "groups": {str(k): sum(r["cells"] for r in v) for k, v in groups.items()},
+                   "graph": not args.no_graph, "autotune": not args.no_autotune,
+                   "launch_shapes": {str(k): v for k, v in b.shapes.items()},
+                   "cg_iterations_per_step": cg // args.steps,
+                   "voxel_iters_per_s": vox_iters / wall},
+        "roofline": {"bound": "hbm", "kernel": "whole tangent job (all CG passes, effective)",
+                     "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +204,13 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
+    ap.add_argument("--workload", default="nh128", choices=["nh128", "uq256", "tangents32"],
+                    help="nh128: the Newton-CG solve (default); uq256: tangents of 256 cells of uneven size; "
+                         "tangents32: tangents of 1024 cells of 32^3")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--max-gb", type=float, default=96.0, help="workspace budget per multi-cell handle")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -139,6 +241,19 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
                           "copy_GBs": round(2 * src.numel() * 8 / t / 1e9, 1)}))
         return
+    if args.workload == "uq256":
+        cells = workloads.workload_uq_cells(256)
+        log("workload generated")
+        return bench_cells(args, "256 uneven cells", cells,
+                           "uq256: 256 small-strain linear elastic cells, edge drawn from {32,48,64,96}, "
+                           "thresholded Gaussian random fields (l ~ U[4,12], stiff fraction ~ U[0.1,0.5]), "
+                           "E_matrix ~ lognormal(0,0.2), E_stiff = 10 E_matrix, nu=0.3, 6 unit loads each, CG tol 1e-10")
+    if args.workload == "tangents32":
+        cells = workloads.workload_tangent_cells(1024)
+        log("workload generated")
+        return bench_cells(args, "1024 cells of 32^3", cells,
+                           "tangents32: 1024 small-strain linear elastic 32^3 cells, Gaussian random field "
+                           "(l=8) top 30%% stiff, E1, E2 ~ lognormal(0,0.5), nu=0.3, 6 unit loads each, CG tol 1e-10")
     n = args.n
     w = workloads.workload_neohookean3d(n=n)
     shape = w["shape"]

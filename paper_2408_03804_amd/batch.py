@@ -68,7 +68,8 @@ class TangentBatcher:
         return h
 
     def tangents(self, cells):
-        """cells: sequence of dicts with 'phase' (grid array) and 'table' ((nphase, 2) lam, mu).
+        """cells: sequence of dicts with 'phase' (grid array, numpy or torch, host or device) and
+        'table' ((nphase, 2) lam, mu).
 
         Returns (C, info): C is an array (len(cells), c, c) when every cell has the same c
         (otherwise a list), info a list of per-chunk records (shape, cells, cg total, seconds).
@@ -77,7 +78,7 @@ class TangentBatcher:
 
         groups = OrderedDict()
         for i, cell in enumerate(cells):
-            groups.setdefault(tuple(np.shape(cell["phase"])), []).append(i)
+            groups.setdefault(tuple(cell["phase"].shape), []).append(i)
         out = [None] * len(cells)
         info = []
         for shape, idx in groups.items():
@@ -86,8 +87,8 @@ class TangentBatcher:
                 chunk = idx[s:s + k]
                 self._tune = None
                 h = self.handle(shape, len(chunk))
-                phase = torch.stack([torch.as_tensor(np.asarray(cells[i]["phase"], dtype=np.uint8))
-                                     for i in chunk]).to(h.device)
+                phase = torch.stack([torch.as_tensor(cells[i]["phase"]).to(device=h.device, dtype=torch.uint8)
+                                     for i in chunk])
                 table = np.stack([np.asarray(cells[i]["table"], dtype=np.float64) for i in chunk])
                 h.set_material(phase, table)
                 if self._tune is not None:

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfft_homog.so")
-SOURCES = ["kernels.hip", "fft_homog.hip"]
+SOURCES = ["kernels.hip", "fft_homog.hip", "cnn.hip"]
 HEADERS = ["common.h", "dual.h", "materials.h", "fft_lds.h", "kernels.h"]
 
 FLAGS = [

@@ -196,3 +196,21 @@ def workload_uq_cells(n_cells=256, sizes=(32, 48, 64, 96), seed=0, stiff_ratio=1
         cells.append(dict(shape=(n, n, n), phase=phase, table=table, seed=cell_seed,
                           correlation_length=ell, stiff_fraction=frac))
     return cells
+
+
+def workload_tangent_cells(n_cells=1024, n=32, seed=0, correlation_length=8.0, stiff_fraction=0.30):
+    """Training-style cells for a stiffness surrogate: the 3D Gaussian-random-field generator
+    of the finite-strain workload (l = 8 voxels, top 30 % stiff) at n^3, small-strain linear
+    elastic with Young's moduli E1 (phase 0) and E2 (phase 1, the thresholded top) drawn
+    independently from lognormal(0, 0.5), nu = 0.3 (the spread of the moduli is a reading:
+    the workload statement does not fix it).  Returns a list of dicts like workload_uq_cells.
+    """
+    rng = np.random.default_rng(seed)
+    cells = []
+    for i in range(n_cells):
+        E1, E2 = (float(v) for v in rng.lognormal(0.0, 0.5, size=2))
+        cell_seed = int(rng.integers(0, 2 ** 31 - 1))
+        phase = grf_two_phase((n, n, n), correlation_length, stiff_fraction, cell_seed)
+        cells.append(dict(shape=(n, n, n), phase=phase, table=np.array([lame(E1, 0.3), lame(E2, 0.3)]),
+                          seed=cell_seed, correlation_length=correlation_length, stiff_fraction=stiff_fraction))
+    return cells

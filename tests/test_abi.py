@@ -94,3 +94,32 @@ def test_strerror_names_every_status():
     lib = binding.load_library()
     for code in range(9):
         assert lib.fft_homog_strerror(code).decode() != "unknown status"
+
+
+def test_surrogate_header_matches_binding_and_library():
+    from paper_2408_03804_amd import surrogate
+    text = open(os.path.join(ROOT, "include", "fft_homog_cnn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(fft_homog_cnn_[a-z_]+)\s*\(", text)))
+    assert names == sorted(surrogate.CNN_EXPORTS)
+    lib = surrogate.load_library()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert ctypes.sizeof(surrogate.CnnDesc) == 40
+
+
+def test_surrogate_sizes_are_host_only():
+    from paper_2408_03804_amd import surrogate
+    lib = surrogate.load_library()
+    d = surrogate.make_desc()
+    cnt = ctypes.c_size_t(0)
+    assert lib.fft_homog_cnn_param_count(ctypes.byref(d), ctypes.byref(cnt)) == 0
+    assert cnt.value == 1234005
+    nb = ctypes.c_size_t(0)
+    assert lib.fft_homog_cnn_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == 0
+    assert 4 * 4 * cnt.value < nb.value < (2 << 30)
+    for bad in (dict(n=24), dict(n=8), dict(channels=(2, 32, 64, 128, 256)), dict(max_batch=0), dict(n_out=0)):
+        kw = dict(n=32, channels=(1, 32, 64, 128, 256), hidden=256, n_feat=1, n_out=21, max_batch=256)
+        kw.update(bad)
+        d = surrogate.make_desc(**kw)
+        assert lib.fft_homog_cnn_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == 1, bad

@@ -53,7 +53,7 @@ bool factorize(int n, int* radix, int* nst) {
 }
 
 struct Layout {
-  size_t F, x, r, p, spec, kst, phase, density, scale, table, tw[3], partials, state, results, flags, total;
+  size_t F, x, r, p, spec, kst, phase, density, scale, table, tw[3], partials, state, active, results, flags, total;
   int cells;  // independent cells (microstructures) of this grid held by the handle
   int B, R, TXm, TXo, nblk_x, nblk_vox;
   size_t n_results;
@@ -204,6 +204,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->n_partials = np;
   L->partials = take(np * sizeof(double));
   L->state = take((size_t)L->B * sizeof(CgState));
+  L->active = take((size_t)L->B * sizeof(int));
   L->n_results = std::max((size_t)kResults, (size_t)L->cells * C * C);
   L->results = take(L->n_results * sizeof(double));
   L->flags = take(16 * sizeof(int));
@@ -225,6 +226,7 @@ struct fft_homog {
   double2* spec;
   uint8_t* phase;
   int* flags;
+  int* active;  // right-hand sides still running, for compacted launches
   CgState* st;
   AxisPlan plan[3];
   MatParams mat;
@@ -234,6 +236,7 @@ struct fft_homog {
   CgState* h_st;
   double* h_results;
   int* h_flags;
+  int* h_active;
   hipEvent_t ev0, ev1;
   // replayable chunks of CG iterations (FLAG_GRAPH): [0] one right-hand side, [1] the batch
   hipStream_t cap;
@@ -307,15 +310,20 @@ AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inpl
   a.inplace = inplace >= 0 ? inplace : (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
   a.spec = h->spec;
   a.st = st;
+  a.active = nullptr;
   return a;
 }
 
 // spectral part shared by every operator application: y, outer (+G-hat), y^-1
-hipError_t enqueue_spectral(fft_homog_t* h, int mode, int B, const CgState* st, hipStream_t s) {
+hipError_t enqueue_spectral(fft_homog_t* h, int mode, int B, const CgState* st, hipStream_t s,
+                            const int* active = nullptr) {
   hipError_t e = hipSuccess;
-  if (h->g.ndim == 3 && mode != OUTER_INV) e = launch_mid(-1, axis_args(h, 1, h->L.TXm, st), B, s);
-  if (e == hipSuccess) e = launch_outer(mode, axis_args(h, h->g.ndim - 1, h->L.TXo, st), B, s);
-  if (e == hipSuccess && h->g.ndim == 3 && mode != OUTER_FWD) e = launch_mid(1, axis_args(h, 1, h->L.TXm, st), B, s);
+  AxisArgs am = axis_args(h, 1, h->L.TXm, st);
+  AxisArgs ao = axis_args(h, h->g.ndim - 1, h->L.TXo, st);
+  am.active = ao.active = active;
+  if (h->g.ndim == 3 && mode != OUTER_INV) e = launch_mid(-1, am, B, s);
+  if (e == hipSuccess) e = launch_outer(mode, ao, B, s);
+  if (e == hipSuccess && h->g.ndim == 3 && mode != OUTER_FWD) e = launch_mid(1, am, B, s);
   return e;
 }
 
@@ -324,20 +332,24 @@ int spectral_middle(fft_homog_t* h, int mode, int B, const CgState* st) {
   return FFT_HOMOG_OK;
 }
 
-// m CG iterations on every running right-hand side, enqueued on stream s
-hipError_t enqueue_cg_iters(fft_homog_t* h, int B, int m, hipStream_t s) {
+// m CG iterations, enqueued on stream s, over B launch slots: slot i is right-hand side
+// active[i] (active == nullptr: i).  Right-hand sides that stop inside the chunk make
+// their blocks return at once.
+hipError_t enqueue_cg_iters(fft_homog_t* h, int B, int m, hipStream_t s, const int* active = nullptr) {
   const int prod = h->desc.k_mode == FFT_HOMOG_K_STORED ? PROD_CGOP_STORED : PROD_CGOP;
   XFwdArgs a = xfwd_args(h);
   a.in = h->r;
   a.p = h->p;
+  a.active = active;
   XInvArgs ai = xinv_args(h);
+  ai.active = active;
   hipError_t e = hipSuccess;
   for (int i = 0; i < m && e == hipSuccess; ++i) {
     e = launch_xfwd(prod, h->matcode, a, B, s);
-    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, s);
-    if (e == hipSuccess) e = enqueue_spectral(h, OUTER_PROJECT, B, h->st, s);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, s, active);
+    if (e == hipSuccess) e = enqueue_spectral(h, OUTER_PROJECT, B, h->st, s, active);
     if (e == hipSuccess) e = launch_xinv(CONS_CGUPD, ai, B, s);
-    if (e == hipSuccess) e = launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, s);
+    if (e == hipSuccess) e = launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, s, active);
   }
   return e;
 }
@@ -354,9 +366,9 @@ void drop_graphs(fft_homog_t* h) {
 // captured (on a private stream, which the capture does not run) from the same
 // launches; every kernel argument is a workspace pointer or a launch-shape
 // constant, so the graph stays valid until the material or the shape changes.
-int cg_chunk(fft_homog_t* h, int B, int m) {
-  if (!(h->desc.flags & FFT_HOMOG_FLAG_GRAPH) || m != kChunk) {
-    FH_CK(enqueue_cg_iters(h, B, m, h->stream));
+int cg_chunk(fft_homog_t* h, int B, int m, int nrun, const int* active) {
+  if (!(h->desc.flags & FFT_HOMOG_FLAG_GRAPH) || m != kChunk || active) {
+    FH_CK(enqueue_cg_iters(h, nrun, m, h->stream, active));
     return FFT_HOMOG_OK;
   }
   const int k = B == 1 ? 0 : 1;
@@ -413,19 +425,26 @@ int rhs_chain(fft_homog_t* h, int prod, int B, const double* unit) {
   return read_states(h, B);
 }
 
-// conjugate gradients on all running right-hand sides until none is running
+// Conjugate gradients on all running right-hand sides until none is running.  Once some
+// have stopped, the launches cover only the running ones (their indices are uploaded
+// before each chunk), so a batch's slow tail does not pay for its finished members.
 int cg_loop(fft_homog_t* h, int B) {
   for (;;) {
-    bool running = false;
+    int nrun = 0;
     int done = 1 << 30;
     for (int b = 0; b < B; ++b)
       if (h->h_st[b].status == CG_RUNNING) {
-        running = true;
+        h->h_active[nrun++] = b;
         done = std::min(done, h->h_st[b].iters);
       }
-    if (!running) return FFT_HOMOG_OK;
+    if (nrun == 0) return FFT_HOMOG_OK;
     const int m = std::min(kChunk, std::max(1, h->desc.max_cg - done));
-    int rc = cg_chunk(h, B, m);
+    const int* act = nullptr;
+    if (nrun < B) {
+      FH_CK(hipMemcpyAsync(h->active, h->h_active, nrun * sizeof(int), hipMemcpyHostToDevice, h->stream));
+      act = h->active;
+    }
+    int rc = cg_chunk(h, B, m, nrun, act);
     if (rc) return rc;
     rc = read_states(h, B);
     if (rc) return rc;
@@ -527,6 +546,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   h->st = (CgState*)(h->ws + L.state);
   h->results = (double*)(h->ws + L.results);
   h->flags = (int*)(h->ws + L.flags);
+  h->active = (int*)(h->ws + L.active);
   h->solved_ok = false;
   for (int k = 0; k < kMaxC; ++k) h->macro_cur[k] = 0.0;
   if (!h->g.small)
@@ -541,13 +561,15 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   h->gexec[0] = h->gexec[1] = nullptr;
   h->gB[0] = h->gB[1] = 0;
 
-  hipError_t e = hipHostMalloc((void**)&h->h_st, L.B * sizeof(CgState) + L.n_results * sizeof(double) + 64, 0);
+  hipError_t e = hipHostMalloc((void**)&h->h_st,
+                               L.B * sizeof(CgState) + L.n_results * sizeof(double) + 64 + L.B * sizeof(int), 0);
   if (e != hipSuccess) {
     delete h;
     return create_fail(FFT_HOMOG_EDEVICE, "hipHostMalloc", e);
   }
   h->h_results = (double*)((char*)h->h_st + L.B * sizeof(CgState));
   h->h_flags = (int*)(h->h_results + L.n_results);
+  h->h_active = h->h_flags + 16;
   const char* step = "hipEventCreate";
   e = hipEventCreate(&h->ev0);
   if (e == hipSuccess) e = hipEventCreate(&h->ev1);

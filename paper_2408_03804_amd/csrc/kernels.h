@@ -25,6 +25,7 @@ struct XFwdArgs {
   double2* spec;         // [B][c][Nh]
   MatParams mat;          // cell 0; cell i has its phase map at phase + i N, its table at table + i 2 kMaxPhase
   int per_inst;          // right-hand sides per cell of a multi-cell batch (0: one cell, every b uses cell 0)
+  const int* active;     // nullable: right-hand side of launch index blockIdx.y (the running ones)
   CgState* st;           // per right-hand side
   double* partials;      // [B][nblocks]
   double unit[kMaxC];    // TRHS: load l of a cell is unit[l] * e_l in the packed basis; ADJ: packed W
@@ -42,6 +43,7 @@ struct XInvArgs {
   double* out;           // IDENT output [B][c][N]
   double* x;             // RHS: CG solution [B][c][N], set to zero
   double* r;             // CG residual [B][c][N]
+  const int* active;     // nullable: right-hand side of launch index blockIdx.y
   CgState* st;
   double* partials;
   double scale;          // 1 / N
@@ -55,6 +57,7 @@ struct AxisArgs {
   int inplace;
   double2* spec;
   const CgState* st;     // nullable: skip right-hand sides whose CG is not running
+  const int* active;     // nullable: right-hand side of each launch-index group
 };
 
 // dynamic LDS bytes of each pass; `inplace` drops the ping-pong buffer
@@ -70,7 +73,9 @@ hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t 
 hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s);
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s);
 hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s);
-hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s);
+// B blocks; block i reduces right-hand side active[i] (active nullable: i)
+hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s,
+                            const int* active = nullptr);
 // x += alpha p for every right-hand side whose CG stopped after at least one full iteration
 hipError_t launch_cg_finish(double* x, const double* p, const CgState* st, const Geom& g, int B, hipStream_t s);
 

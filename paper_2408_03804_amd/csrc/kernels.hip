@@ -93,7 +93,7 @@ template <int PROD, int MAT, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
   constexpr bool CGOP = (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED);
-  const int b = blockIdx.y;
+  const int b = a.active ? a.active[blockIdx.y] : (int)blockIdx.y;
   if (CGOP) {
     if (a.st[b].status != CG_RUNNING) return;
   }
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 // ============================================================================
 template <int CONS, int C>
 __global__ void __launch_bounds__(kThreads) k_xinv(XInvArgs a) {
-  const int b = blockIdx.y;
+  const int b = a.active ? a.active[blockIdx.y] : (int)blockIdx.y;
   if (CONS == CONS_CGUPD) {
     if (a.st[b].status != CG_RUNNING) return;
   }
@@ -417,7 +417,9 @@ __global__ void __launch_bounds__(kThreads) k_cg_finish(double* x, const double*
 template <int DIR>
 __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   const Geom& g = a.g;
-  const int b = blockIdx.z / g.c;
+  const int vb = blockIdx.z / g.c;
+  const int comp = blockIdx.z - vb * g.c;
+  const int b = a.active ? a.active[vb] : vb;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
   const int kx0 = blockIdx.x * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
@@ -425,7 +427,7 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   extern __shared__ double2 smem[];
   double2* A = smem;
   double2* Bf = smem + (size_t)ny * tw;
-  const long long base = (long long)blockIdx.z * g.Nh + (long long)blockIdx.y * ny * g.nxp + kx0;
+  const long long base = ((long long)b * g.c + comp) * g.Nh + (long long)blockIdx.y * ny * g.nxp + kx0;
   const FastDiv fdt = make_fastdiv((unsigned)tw);
   for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
     const int y = (int)fdiv((unsigned)t, fdt);
@@ -541,8 +543,9 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
       bz = l2 / (gridDim.x * gridDim.y);
     }
   }
-  const int b = bz / NGRP;
-  const int grp = bz - b * NGRP;
+  const int vb = bz / NGRP;
+  const int grp = bz - vb * NGRP;
+  const int b = a.active ? a.active[vb] : vb;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
   const int kx0 = bx * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
@@ -635,9 +638,10 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
 constexpr int kReduceThreads = 1024;
 
 template <int WHAT>
-__global__ void __launch_bounds__(kReduceThreads) k_cg_reduce(CgState* st, const double* partials, int nblocks) {
+__global__ void __launch_bounds__(kReduceThreads) k_cg_reduce(CgState* st, const double* partials, int nblocks,
+                                                                const int* active) {
   __shared__ double red[kReduceThreads / 64];
-  const int b = blockIdx.x;
+  const int b = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgState& S = st[b];
   if ((WHAT == RED_PQ || WHAT == RED_RR) && S.status != CG_RUNNING) return;
   double acc = 0.0;
@@ -1013,12 +1017,13 @@ hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s) {
+hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int nblocks, int B, hipStream_t s,
+                            const int* active) {
   switch (what) {
-    case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
-    case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
-    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
-    case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks); break;
+    case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
+    case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
+    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
+    case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

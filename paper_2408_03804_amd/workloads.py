@@ -101,8 +101,16 @@ def threshold_top(field, fraction):
     """Phase 1 on exactly round(fraction*N) voxels with the largest values (ties: flat index)."""
     flat = field.reshape(-1)
     m = int(round(fraction * flat.size))
-    order = np.argsort(-flat, kind="stable")
     phase = np.zeros(flat.size, dtype=np.uint8)
+    if 0 < m < flat.size:
+        # the m largest values; equal to the stable descending sort's first m unless the
+        # value at the cut is shared, which then decides by flat index
+        top = np.argpartition(-flat, m - 1)[:m]
+        cut = flat[top].min()
+        if np.count_nonzero(flat >= cut) == m and np.count_nonzero(flat == cut) == 1:
+            phase[top] = 1
+            return phase.reshape(field.shape)
+    order = np.argsort(-flat, kind="stable")
     phase[order[:m]] = 1
     return phase.reshape(field.shape)
 
@@ -198,19 +206,45 @@ def workload_uq_cells(n_cells=256, sizes=(32, 48, 64, 96), seed=0, stiff_ratio=1
     return cells
 
 
-def workload_tangent_cells(n_cells=1024, n=32, seed=0, correlation_length=8.0, stiff_fraction=0.30):
-    """Training-style cells for a stiffness surrogate: the 3D Gaussian-random-field generator
-    of the finite-strain workload (l = 8 voxels, top 30 % stiff) at n^3, small-strain linear
+def _grf_filter(w, correlation_length, axes):
+    """Filter white noise w over `axes` by sqrt(S(k)), S(k) = exp(-l^2 |k|^2 / 2), and standardise
+    each field (the other axes index independent fields)."""
+    import scipy.fft
+
+    shape = [w.shape[a] for a in axes]
+    what = scipy.fft.rfftn(w, axes=axes, workers=-1)
+    ks = [2.0 * np.pi * np.fft.fftfreq(s) for s in shape[:-1]] + [2.0 * np.pi * np.fft.rfftfreq(shape[-1])]
+    k2 = np.zeros([what.shape[a] for a in axes])
+    for ax, k in enumerate(ks):
+        bs = [1] * len(axes)
+        bs[ax] = k.shape[0]
+        k2 = k2 + k.reshape(bs) ** 2
+    g = scipy.fft.irfftn(what * np.exp(-0.25 * correlation_length ** 2 * k2), s=shape, axes=axes, workers=-1)
+    g -= g.mean(axis=axes, keepdims=True)
+    g /= g.std(axis=axes, keepdims=True)
+    return g
+
+
+def workload_tangent_cells(n_cells=1024, n=32, seed=0, correlation_length=8.0, stiff_fraction=0.30, chunk=256):
+    """Training-style cells for a stiffness surrogate: the 3D Gaussian-random-field recipe of
+    the finite-strain workload (l = 8 voxels, top 30 % stiff) at n^3, small-strain linear
     elastic with Young's moduli E1 (phase 0) and E2 (phase 1, the thresholded top) drawn
     independently from lognormal(0, 0.5), nu = 0.3 (the spread of the moduli is a reading:
-    the workload statement does not fix it).  Returns a list of dicts like workload_uq_cells.
+    the workload statement does not fix it).  The moduli come from the stream
+    default_rng([seed, 0]); the white noise of cell i is the i-th n^3 block of
+    default_rng([seed, 1]).standard_normal, drawn in chunks of `chunk` cells.
+    Returns a list of dicts like workload_uq_cells.
     """
-    rng = np.random.default_rng(seed)
+    E = np.random.default_rng([seed, 0]).lognormal(0.0, 0.5, size=(n_cells, 2))
+    rng = np.random.default_rng([seed, 1])
     cells = []
-    for i in range(n_cells):
-        E1, E2 = (float(v) for v in rng.lognormal(0.0, 0.5, size=2))
-        cell_seed = int(rng.integers(0, 2 ** 31 - 1))
-        phase = grf_two_phase((n, n, n), correlation_length, stiff_fraction, cell_seed)
-        cells.append(dict(shape=(n, n, n), phase=phase, table=np.array([lame(E1, 0.3), lame(E2, 0.3)]),
-                          seed=cell_seed, correlation_length=correlation_length, stiff_fraction=stiff_fraction))
+    for c0 in range(0, n_cells, chunk):
+        k = min(chunk, n_cells - c0)
+        g = _grf_filter(rng.standard_normal((k, n, n, n)), correlation_length, (1, 2, 3))
+        for j in range(k):
+            i = c0 + j
+            phase = threshold_top(g[j], stiff_fraction)
+            cells.append(dict(shape=(n, n, n), phase=phase,
+                              table=np.array([lame(E[i, 0], 0.3), lame(E[i, 1], 0.3)]), seed=i,
+                              correlation_length=correlation_length, stiff_fraction=stiff_fraction))
     return cells

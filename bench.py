@@ -194,6 +194,124 @@ def bench_cells(args, name, cells, description):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """Stiffness surrogate against the solver on 32^3 cells: training data from the solver, training,
+    held-out error, and tangents/s of both (surrogate with its indicator and solver fallback)."""
+    import torch
+
+    from paper_2408_03804_amd import workloads
+    from paper_2408_03804_amd.batch import TangentBatcher
+    from paper_2408_03804_amd.surrogate import StiffnessSurrogate, full6
+
+    ntr, nte = args.train_cells, args.test_cells
+    t0 = time.perf_counter()
+    cells = workloads.workload_tangent_cells(ntr + nte, seed=0)
+    phase = torch.stack([torch.as_tensor(c["phase"]) for c in cells]).to("cuda:0")
+    tables = np.stack([c["table"] for c in cells])
+    del cells
+    log("%d cells generated in %.1f s" % (ntr + nte, time.perf_counter() - t0))
+
+    # training data and held-out references from the FP64 solver
+    b = TangentBatcher(tol_cg=1e-10, max_cg=20000, graph=True, autotune=True, max_bytes=int(48 << 30),
+                       device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C_all, info = b.tangents([dict(phase=phase[i], table=tables[i]) for i in range(ntr + nte)])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    b.close()
+    log("solver tangents of %d cells: %.1f s (%.1f tangents/s)" % (ntr + nte, t_data, (ntr + nte) / t_data))
+
+    sur = StiffnessSurrogate(n=32, max_batch=max(args.batch, nte), device="cuda:0", seed=0, members=args.members)
+    t0 = time.perf_counter()
+    hist = sur.fit(phase[:ntr], tables[:ntr], C_all[:ntr], epochs=args.epochs, batch=args.batch, lr=args.lr,
+                   log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("training: %.1f s, final losses %s" % (t_train, [h[-1] for h in hist]))
+
+    tp, tt, Ct = phase[ntr:], tables[ntr:], C_all[ntr:]
+    kw = dict(tol=args.check_tol, max_spread=args.max_spread)
+    for _ in range(2):
+        sur.predict_checked(tp, tt, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C21, ok = sur.predict_checked(tp, tt, **kw)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / args.steps
+    Cp = full6(C21.cpu().numpy().astype(np.float64))
+    okh = ok.cpu().numpy().astype(bool)
+    err = np.linalg.norm((Cp - Ct).reshape(nte, -1), axis=1) / np.linalg.norm(Ct.reshape(nte, -1), axis=1)
+
+    # the solver alone on the held-out cells, and on the cells the indicator rejects
+    b = TangentBatcher(tol_cg=1e-10, max_cg=20000, graph=True, autotune=True, max_bytes=int(48 << 30),
+                       device="cuda:0")
+    test_cells = [dict(phase=tp[i], table=tt[i]) for i in range(nte)]
+    b.tangents(test_cells)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.tangents(test_cells)
+    torch.cuda.synchronize()
+    t_sol = (time.perf_counter() - t0) / args.steps
+    rej = [test_cells[i] for i in np.nonzero(~okh)[0]]
+    t_fb = 0.0
+    if rej:
+        b.tangents(rej)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.tangents(rej)
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+    b.close()
+    parts = sur.indicator_parts(tp, tt, **kw)
+    reasons = {k: int((~v).sum()) for k, v in parts.items()}
+    lc = np.abs(StiffnessSurrogate.features(tt)[:, 0])
+    edges = np.percentile(lc, [0, 33.3, 66.7, 100])
+    by_contrast = []
+    for lo_, hi_ in zip(edges[:-1], edges[1:]):
+        sel = (lc >= lo_) & (lc <= hi_)
+        by_contrast.append({"abs_log_contrast": [round(float(lo_), 3), round(float(hi_), 3)],
+                            "mean": float(err[sel].mean()), "p95": float(np.percentile(err[sel], 95)),
+                            "rejected": int((~okh[sel]).sum()), "cells": int(sel.sum())})
+    final_err = err.copy()
+    final_err[~okh] = 0.0  # rejected cells are answered by the solver
+    out = {
+        "metric": "homogenized tangents/s, stiffness surrogate with solver fallback vs FP64 solver (32^3)",
+        "value": nte / (t_sur + t_fb),
+        "unit": "tangents/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": (t_sur + t_fb) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "surrogate32: %d training + %d held-out small-strain linear elastic 32^3 cells "
+                               "(Gaussian random field l=8, top 30%% stiff, E1, E2 ~ lognormal(0,0.5), nu=0.3); "
+                               "CNN 1-32-64-128-256 stride-2 3^3 conv blocks, GELU, mean pool, MLP 257-256-21, "
+                               "bf16 MFMA / fp32 accumulation, Adam %d epochs batch %d, ensemble of %d, indicator: "
+                               "Voigt-Reuss bounds (tol %g), central 95%% of the training contrasts, member spread <= %g"
+                               % (ntr, nte, args.epochs, args.batch, args.members, args.check_tol, args.max_spread),
+                   "solver_tangents_per_s": nte / t_sol,
+                   "surrogate_only_tangents_per_s": nte / t_sur,
+                   "speedup_vs_solver": t_sol / (t_sur + t_fb),
+                   "rel_error_frobenius": {"mean": float(err.mean()), "median": float(np.median(err)),
+                                           "p95": float(np.percentile(err, 95)), "max": float(err.max()),
+                                           "frac_le_2pct": float((err <= 0.02).mean())},
+                   "after_fallback": {"mean": float(final_err.mean()), "p95": float(np.percentile(final_err, 95)),
+                                      "frac_le_2pct": float((final_err <= 0.02).mean())},
+                   "rejected_by_indicator": int((~okh).sum()),
+                   "error_by_contrast_tercile": by_contrast,
+                   "rejections_by_test": reasons,
+                   "accepted_error": {"mean": float(err[okh].mean()) if okh.any() else None,
+                                      "p95": float(np.percentile(err[okh], 95)) if okh.any() else None,
+                                      "max": float(err[okh].max()) if okh.any() else None},
+                   "training_s": t_train, "data_generation_s": t_data,
+                   "final_train_loss": [h[-1] for h in hist]},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    sur.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,7 +322,15 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
-    ap.add_argument("--workload", default="nh128", choices=["nh128", "uq256", "tangents32"],
+    ap.add_argument("--train-cells", type=int, default=20000)
+    ap.add_argument("--test-cells", type=int, default=1024)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--check-tol", type=float, default=0.02)
+    ap.add_argument("--max-spread", type=float, default=0.03)
+    ap.add_argument("--members", type=int, default=2)
+    ap.add_argument("--workload", default="nh128", choices=["nh128", "uq256", "tangents32", "surrogate32"],
                     help="nh128: the Newton-CG solve (default); uq256: tangents of 256 cells of uneven size; "
                          "tangents32: tangents of 1024 cells of 32^3")
     ap.add_argument("--no-graph", action="store_true")
@@ -241,6 +367,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
                           "copy_GBs": round(2 * src.numel() * 8 / t / 1e9, 1)}))
         return
+    if args.workload == "surrogate32":
+        return bench_surrogate(args)
     if args.workload == "uq256":
         cells = workloads.workload_uq_cells(256)
         log("workload generated")

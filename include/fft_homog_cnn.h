@@ -79,14 +79,19 @@ int fft_homog_cnn_adam_step(fft_homog_cnn_t* h, float lr, float beta1, float bet
 
 /* Error indicator of predicted stiffnesses, per sample (ok[b] = 1 passes, 0 fails):
  *   C (f32[batch][21], upper triangle row by row of the 6x6 Voigt tangent with engineering
- *   shear) must be positive definite and lie between the Reuss and Voigt bounds of its cell:
- *   (1 + tol) C_Voigt - C and C - (1 - tol) C_Reuss positive definite, the bounds taken from
+ *   shear) must be positive definite and lie between the Reuss and Voigt bounds of its cell
+ *   up to a slack s = tol |C_Voigt|_F (Frobenius norm): C_Voigt - C + s I and C - C_Reuss + s I
+ *   positive definite, the bounds taken from
  *   the phase volume fractions of phase (u8[batch][n^3]) and the isotropic phase moduli
  *   lam_mu (f32[batch][2][2] = (lam, mu) of phase 0 and phase 1); and feat[b][0] must lie
- *   in [feat_lo, feat_hi] (the range seen in training). */
+ *   in [feat_lo, feat_hi] (the range seen in training).
+ *   C2 (nullable, f32[batch][21]): the prediction of a second, independently trained network.
+ *   C is then replaced in place by (C + C2) / 2, the tests above apply to that mean, and the
+ *   spread |C - C2| / |(C + C2) / 2| (2-norms over the 21 components) must not exceed
+ *   max_spread. */
 int fft_homog_cnn_check(fft_homog_cnn_t* h, const uint8_t* phase, const float* lam_mu,
-                        const float* feat, const float* C, int batch, float tol, float feat_lo,
-                        float feat_hi, int* ok);
+                        const float* feat, float* C, const float* C2, int batch, float tol,
+                        float feat_lo, float feat_hi, float max_spread, int* ok);
 
 /* Device time (ms, HIP events) of the last forward and of the last loss_grad call. */
 int fft_homog_cnn_last_ms(const fft_homog_cnn_t* h, double* forward_ms, double* train_ms);

@@ -445,8 +445,8 @@ __device__ void iso6(double lam, double mu, double (*C)[6]) {
 }
 
 // one block per sample: volume fraction, Voigt / Reuss bounds, Cholesky tests, feature range
-__global__ void k_check(const uint8_t* phase, long long Nv, const float* lm, const float* feat, int nf, const float* C21,
-                        float tol, float lo, float hi, int* ok) {
+__global__ void k_check(const uint8_t* phase, long long Nv, const float* lm, const float* feat, int nf, float* C21,
+                        const float* C2, float tol, float lo, float hi, float max_spread, int* ok) {
   __shared__ double red[kT];
   const int b = blockIdx.x;
   double cnt = 0.0;
@@ -468,18 +468,37 @@ __global__ void k_check(const uint8_t* phase, long long Nv, const float* lm, con
   double Cv[6][6], Cr[6][6], Cp[6][6], A[6][6];
   iso6(lv, mv, Cv);
   iso6(lr, mr, Cr);
+  // with a second ensemble member: the prediction becomes the mean of the two, and their
+  // spread (2-norm of the difference of the 21 components over that of the mean) is tested
+  double d2 = 0.0, n2 = 0.0;
   int k = 0;
   for (int i = 0; i < 6; ++i)
     for (int j = i; j < 6; ++j) {
-      Cp[i][j] = Cp[j][i] = C21[(long long)b * 21 + k];
+      double c = C21[(long long)b * 21 + k];
+      if (C2) {
+        const double c2 = C2[(long long)b * 21 + k];
+        d2 += (c - c2) * (c - c2);
+        c = 0.5 * (c + c2);
+        n2 += c * c;
+        C21[(long long)b * 21 + k] = (float)c;
+      }
+      Cp[i][j] = Cp[j][i] = c;
       ++k;
     }
   bool good = spd6(Cp);
+  if (C2) good = good && (sqrt(d2) <= (double)max_spread * sqrt(n2));
+  // bounds with a slack of tol |C_Voigt|_F in every direction (prediction errors are measured
+  // in that norm; a per-direction relative slack would reject small errors in the soft
+  // shear directions)
+  double fro = 0.0;
   for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) A[i][j] = (1.0 + tol) * Cv[i][j] - Cp[i][j];
+    for (int j = 0; j < 6; ++j) fro += Cv[i][j] * Cv[i][j];
+  const double slack = (double)tol * sqrt(fro);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) A[i][j] = Cv[i][j] - Cp[i][j] + (i == j ? slack : 0.0);
   good = good && spd6(A);
   for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) A[i][j] = Cp[i][j] - (1.0 - tol) * Cr[i][j];
+    for (int j = 0; j < 6; ++j) A[i][j] = Cp[i][j] - Cr[i][j] + (i == j ? slack : 0.0);
   good = good && spd6(A);
   if (nf > 0) {
     const float x = feat[(long long)b * nf];
@@ -905,13 +924,14 @@ int fft_homog_cnn_adam_step(fft_homog_cnn_t* h, float lr, float beta1, float bet
   return FFT_HOMOG_OK;
 }
 
-int fft_homog_cnn_check(fft_homog_cnn_t* h, const uint8_t* phase, const float* lam_mu, const float* feat, const float* C,
-                        int batch, float tol, float lo, float hi, int* ok) {
+int fft_homog_cnn_check(fft_homog_cnn_t* h, const uint8_t* phase, const float* lam_mu, const float* feat, float* C,
+                        const float* C2, int batch, float tol, float lo, float hi, float max_spread, int* ok) {
   if (!h || !phase || !lam_mu || !C || !ok || (h->d.n_feat > 0 && !feat)) return FFT_HOMOG_EINVAL;
   if (h->d.n_out != 21) return FFT_HOMOG_EINVAL;
   if (batch < 1) return FFT_HOMOG_EINVAL;
   const long long Nv = (long long)h->d.n * h->d.n * h->d.n;
-  hipLaunchKernelGGL(k_check, dim3(batch), dim3(kT), 0, h->s, phase, Nv, lam_mu, feat, h->d.n_feat, C, tol, lo, hi, ok);
+  hipLaunchKernelGGL(k_check, dim3(batch), dim3(kT), 0, h->s, phase, Nv, lam_mu, feat, h->d.n_feat, C, C2, tol, lo, hi,
+                     max_spread, ok);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(h->s));
   return FFT_HOMOG_OK;

@@ -4,9 +4,10 @@
 optimizer run in the HIP library).  ``StiffnessSurrogate`` holds the data
 conventions: input = phase indicator of an n^3 cell plus log(E2/E1); output =
 the 21 upper-triangle components of the 6x6 homogenized stiffness divided by
-E1 (linear elasticity is homogeneous of degree one in the moduli), standardised
-per component during training and un-standardised by folding the scales into
-the last layer afterwards.  Samples that fft_homog_cnn_check rejects go to the
+sqrt(mu_Voigt mu_Reuss) of the cell (linear elasticity is homogeneous of degree
+one in the moduli, and this scale keeps the targets O(1) at any contrast),
+standardised per component during training and un-standardised by folding the
+scales into the last layer afterwards.  Samples that fft_homog_cnn_check rejects go to the
 FP64 solver (multi-cell tangent handles).
 """
 
@@ -50,7 +51,7 @@ def load_library():
         "fft_homog_cnn_forward": (I, [P, P, P, P, P, I]),
         "fft_homog_cnn_loss_grad": (I, [P, P, P, P, I, ctypes.POINTER(F), P]),
         "fft_homog_cnn_adam_step": (I, [P, F, F, F, F]),
-        "fft_homog_cnn_check": (I, [P, P, P, P, P, I, F, F, F, P]),
+        "fft_homog_cnn_check": (I, [P, P, P, P, P, P, I, F, F, F, F, P]),
         "fft_homog_cnn_last_ms": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "fft_homog_cnn_destroy": (None, [P]),
         "fft_homog_cnn_debug_gemm": (I, [P, I, I, I, P, LL, LL, P, LL, LL, P, I]),
@@ -160,15 +161,18 @@ class CNN:
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._check(self.L.fft_homog_cnn_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))
 
-    def check(self, phase, lam_mu, feat, C21, tol=0.0, feat_lo=-1e30, feat_hi=1e30):
+    def check(self, phase, lam_mu, feat, C21, tol=0.0, feat_lo=-1e30, feat_hi=1e30, C2=None, max_spread=1e30):
+        """Indicator per sample; with C2, C21 (a device f32 tensor) is replaced by the ensemble mean."""
         ph = self._u8(phase)
         B = ph.shape[0]
         lm = self._f32(lam_mu).reshape(B, 4)
         ft = self._f32(feat).reshape(B, self.n_feat) if self.n_feat else None
-        C = self._f32(C21).reshape(B, 21)
+        C = C21 if isinstance(C21, self.torch.Tensor) and C21.dtype == self.torch.float32 and C21.is_cuda \
+            and C21.is_contiguous() else self._f32(C21).reshape(B, 21)
+        C2t = None if C2 is None else self._f32(C2).reshape(B, 21)
         ok = self.torch.empty(B, dtype=self.torch.int32, device=self.device)
-        self._check(self.L.fft_homog_cnn_check(self.h, _p(ph), _p(lm), _p(ft), _p(C), B, float(tol), float(feat_lo),
-                                               float(feat_hi), _p(ok)))
+        self._check(self.L.fft_homog_cnn_check(self.h, _p(ph), _p(lm), _p(ft), _p(C), _p(C2t), B, float(tol),
+                                               float(feat_lo), float(feat_hi), float(max_spread), _p(ok)))
         return ok
 
     def last_ms(self):
@@ -220,13 +224,23 @@ def full6(v):
 
 
 class StiffnessSurrogate:
-    """Train on solver tangents, predict with the CNN, fall back to the solver when the check trips."""
+    """Train on solver tangents, predict with the CNN ensemble, fall back to the solver when the check trips.
 
-    def __init__(self, n=32, max_batch=256, device=None, seed=0, channels=CHANNELS, hidden=256):
-        self.net = CNN(n=n, channels=channels, hidden=hidden, n_feat=1, n_out=21, max_batch=max_batch, device=device)
+    ``members`` networks are trained from different initialisations and batch orders; the
+    prediction is their mean, and with two members their disagreement is part of the
+    error indicator (fft_homog_cnn_check).
+    """
+
+    def __init__(self, n=32, max_batch=256, device=None, seed=0, channels=CHANNELS, hidden=256, members=1):
+        assert members in (1, 2)
+        self.nets = [CNN(n=n, channels=channels, hidden=hidden, n_feat=1, n_out=21, max_batch=max_batch, device=device)
+                     for _ in range(members)]
+        self.net = self.nets[0]
         self.n = n
+        self.seed = seed
         self.shapes = param_shapes(channels, hidden, 1, 21)
-        self.net.set_params(init_params(self.shapes, seed))
+        for i, net in enumerate(self.nets):
+            net.set_params(init_params(self.shapes, seed + 1000 * i))
         self.mean = np.zeros(21)
         self.std = np.ones(21)
         self.feat_range = (-np.inf, np.inf)
@@ -239,75 +253,106 @@ class StiffnessSurrogate:
         return np.log(t[:, 1, 1] / t[:, 0, 1])[:, None]
 
     @staticmethod
-    def scale(tables):
-        """E1 up to the fixed factor 2 (1 + nu): the shear modulus of phase 0."""
-        return np.asarray(tables, dtype=np.float64)[:, 0, 1]
+    def scale(tables, fractions):
+        """Output scale of each cell: sqrt(mu_Voigt mu_Reuss), the geometric mean of the two bounds
+        of the shear modulus for stiff volume fraction f (so that targets are O(1) at any contrast)."""
+        t = np.asarray(tables, dtype=np.float64)
+        f = np.asarray(fractions, dtype=np.float64)
+        m0, m1 = t[:, 0, 1], t[:, 1, 1]
+        mv = (1.0 - f) * m0 + f * m1
+        mr = 1.0 / ((1.0 - f) / m0 + f / m1)
+        return np.sqrt(mv * mr)
 
-    def fit(self, phase, tables, C, epochs=30, batch=256, lr=1e-3, lr_end=1e-5, seed=0, log=None):
+    @staticmethod
+    def fractions(phase):
+        """Stiff volume fraction of each cell (phase maps on the device)."""
+        return phase.reshape(phase.shape[0], -1).float().mean(dim=1).double().cpu().numpy()
+
+    def fit(self, phase, tables, C, epochs=30, batch=256, lr=1e-3, lr_end=1e-5, log=None):
         """phase: device uint8 [S, n, n, n]; tables [S, 2, 2] (lam, mu); C [S, 6, 6] solver tangents."""
         torch = self.net.torch
         feat = self.features(tables)
-        y = upper21(C) / self.scale(tables)[:, None]
+        y = upper21(C) / self.scale(tables, self.fractions(phase))[:, None]
         self.mean = y.mean(axis=0)
         self.std = y.std(axis=0) + 1e-12
-        self.feat_range = (float(feat.min()), float(feat.max()))
+        # inputs are trusted where the training data is dense: the central 95 % of its contrasts
+        self.feat_range = (float(np.percentile(feat, 2.5)), float(np.percentile(feat, 97.5)))
         yt = torch.as_tensor(((y - self.mean) / self.std).astype(np.float32), device=self.net.device)
         ft = torch.as_tensor(feat.astype(np.float32), device=self.net.device)
         S = phase.shape[0]
-        rng = np.random.default_rng(seed)
         steps = epochs * (S // batch)
         hist = []
-        k = 0
-        for ep in range(epochs):
-            perm = torch.as_tensor(rng.permutation(S), device=self.net.device)
-            tot = 0.0
-            for s in range(0, S - batch + 1, batch):
-                idx = perm[s:s + batch]
-                loss, _ = self.net.loss_grad(phase[idx], ft[idx], yt[idx], want_grad=False)
-                # cosine decay of the learning rate
-                lr_k = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / max(1, steps)))
-                self.net.adam_step(lr_k)
-                tot += loss
-                k += 1
-            hist.append(tot / max(1, S // batch))
-            if log:
-                log("epoch %d loss %.4e" % (ep, hist[-1]))
+        for i, net in enumerate(self.nets):
+            rng = np.random.default_rng(self.seed + 1000 * i)
+            k = 0
+            h = []
+            for ep in range(epochs):
+                perm = torch.as_tensor(rng.permutation(S), device=self.net.device)
+                tot = 0.0
+                for s in range(0, S - batch + 1, batch):
+                    idx = perm[s:s + batch]
+                    loss, _ = net.loss_grad(phase[idx], ft[idx], yt[idx], want_grad=False)
+                    # cosine decay of the learning rate
+                    lr_k = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / max(1, steps)))
+                    net.adam_step(lr_k)
+                    tot += loss
+                    k += 1
+                h.append(tot / max(1, S // batch))
+                if log:
+                    log("member %d epoch %d loss %.4e" % (i, ep, h[-1]))
+            hist.append(h)
         return hist
 
     def fold(self):
-        """Fold the target standardisation into the last layer: the network then outputs C21 / E1."""
+        """Fold the target standardisation into the last layer: the networks then output C21 / scale."""
         if self.folded:
             return
-        th = self.net.get_params().cpu().numpy().astype(np.float64)
-        off = 0
-        offs = {}
-        for name, shape in self.shapes:
-            offs[name] = (off, int(np.prod(shape)), shape)
-            off += int(np.prod(shape))
-        o, m, shp = offs["W6"]
-        W6 = th[o:o + m].reshape(shp) * self.std[:, None]
-        th[o:o + m] = W6.reshape(-1)
-        o, m, _ = offs["b6"]
-        th[o:o + m] = th[o:o + m] * self.std + self.mean
-        self.net.set_params(th.astype(np.float32))
+        for net in self.nets:
+            th = net.get_params().cpu().numpy().astype(np.float64)
+            off = 0
+            offs = {}
+            for name, shape in self.shapes:
+                offs[name] = (off, int(np.prod(shape)), shape)
+                off += int(np.prod(shape))
+            o, m, shp = offs["W6"]
+            th[o:o + m] = (th[o:o + m].reshape(shp) * self.std[:, None]).reshape(-1)
+            o, m, _ = offs["b6"]
+            th[o:o + m] = th[o:o + m] * self.std + self.mean
+            net.set_params(th.astype(np.float32))
         self.folded = True
 
-    def predict(self, phase, tables):
-        """C21 (absolute units) of a batch of cells: device tensor [B, 21]."""
+    def predict_checked(self, phase, tables, tol=0.0, max_spread=1e30):
+        """C21 (absolute units; the ensemble mean) of a batch of cells and the per-sample indicator."""
         self.fold()
         torch = self.net.torch
         ft = torch.as_tensor(self.features(tables).astype(np.float32), device=self.net.device)
-        sc = torch.as_tensor(self.scale(tables).astype(np.float32), device=self.net.device)
-        return self.net.forward(phase, ft, sc)
-
-    def predict_checked(self, phase, tables, tol=0.0):
-        """Prediction and the per-sample indicator (1 = accepted)."""
-        torch = self.net.torch
-        C = self.predict(phase, tables)
+        sc = torch.as_tensor(self.scale(tables, self.fractions(phase)).astype(np.float32), device=self.net.device)
+        C = self.nets[0].forward(phase, ft, sc)
+        C2 = self.nets[1].forward(phase, ft, sc) if len(self.nets) > 1 else None
         lm = torch.as_tensor(np.asarray(tables, dtype=np.float32).reshape(-1, 4), device=self.net.device)
-        ft = torch.as_tensor(self.features(tables).astype(np.float32), device=self.net.device)
-        ok = self.net.check(phase, lm, ft, C, tol, self.feat_range[0], self.feat_range[1])
+        ok = self.net.check(phase, lm, ft, C, tol, self.feat_range[0], self.feat_range[1], C2=C2,
+                            max_spread=max_spread)
         return C, ok
 
+    def indicator_parts(self, phase, tables, tol=0.0, max_spread=1e30):
+        """Diagnostics: the indicator's three tests evaluated one at a time (bounds, spread, contrast range)."""
+        self.fold()
+        torch = self.net.torch
+        ft = torch.as_tensor(self.features(tables).astype(np.float32), device=self.net.device)
+        sc = torch.as_tensor(self.scale(tables, self.fractions(phase)).astype(np.float32), device=self.net.device)
+        lm = torch.as_tensor(np.asarray(tables, dtype=np.float32).reshape(-1, 4), device=self.net.device)
+        outs = [net.forward(phase, ft, sc) for net in self.nets]
+        C2 = outs[1] if len(outs) > 1 else None
+        mean = outs[0].clone() if C2 is None else 0.5 * (outs[0] + C2)
+        bounds = self.net.check(phase, lm, ft, mean, tol).cpu().numpy()
+        spread = np.ones_like(bounds)
+        if C2 is not None:
+            # a slack of 10 |C_Voigt| leaves only the positive definiteness of C and the spread
+            spread = self.net.check(phase, lm, ft, outs[0].clone(), 10.0, C2=C2, max_spread=max_spread).cpu().numpy()
+        f = self.features(tables)[:, 0]
+        contrast = ((f >= self.feat_range[0]) & (f <= self.feat_range[1])).astype(int)
+        return {"bounds": bounds.astype(bool), "spread": spread.astype(bool), "contrast": contrast.astype(bool)}
+
     def close(self):
-        self.net.close()
+        for net in self.nets:
+            net.close()

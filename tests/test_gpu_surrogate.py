@@ -196,3 +196,25 @@ def test_indicator_accepts_inside_bounds_and_rejects_outside():
     feat = np.array([[1.0], [1.0], [1.0], [1.0], [5.0]], np.float32)
     ok = h.check(phase, tables.reshape(5, 4), feat, upper21(Cs), 1e-3, 0.0, 2.0).cpu().numpy()
     assert list(ok) == [1, 1, 0, 0, 0]
+
+
+def test_indicator_with_a_second_member_averages_and_tests_the_spread():
+    from paper_2408_03804_amd.surrogate import upper21
+    h, _ = make()
+    rng = np.random.default_rng(13)
+    phase = (rng.random((2, 16, 16, 16)) < 0.3).astype(np.uint8)
+    f1 = phase.reshape(2, -1).mean(axis=1)
+    tables = np.array([[[1.0, 0.8], [6.0, 4.0]]] * 2)
+    C = []
+    for b in range(2):
+        CV, CR = closed_forms.voigt_reuss([closed_forms.isotropic_matrix(1.0, 0.8, 3),
+                                           closed_forms.isotropic_matrix(6.0, 4.0, 3)], [1 - f1[b], f1[b]])
+        C.append(0.5 * (CV + CR))
+    C1 = upper21(np.array(C)).astype(np.float32)
+    C2 = C1 * np.array([[1.02], [1.2]], np.float32)
+    feat = np.ones((2, 1), np.float32)
+    Ct = torch.as_tensor(C1).cuda()
+    ok = h.check(phase, tables.reshape(2, 4), feat, Ct, 0.0, 0.0, 2.0, C2=C2, max_spread=0.05).cpu().numpy()
+    # spreads 0.02 / 1.01 and 0.2 / 1.1 of the mean
+    assert list(ok) == [1, 0]
+    assert np.allclose(Ct.cpu().numpy(), 0.5 * (C1 + C2), rtol=1e-6)

@@ -181,19 +181,31 @@ int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro);
 
 /* Launch shape of the CG passes: shape[0] lines per x-pass block, shape[1] kx bins per
  * y-pass block, shape[2] kx bins per outer-pass block, shape[3..5] 1 if the x, y and outer
- * FFT stages are staged through registers (one LDS buffer) rather than ping-ponged. */
-int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[6]);
+ * FFT stages are staged through registers (one LDS buffer) rather than ping-ponged,
+ * shape[6] the row pitch of the stored half spectrum in bins (nx/2+1 rounded up to a
+ * multiple of 8 by default, or unpadded). */
+int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[7]);
 
-/* Time every candidate launch shape of the CG passes on this handle's grid and batch
- * (each pass over `reps` launches after one warm-up, HIP events on the handle's stream) and
- * keep the fastest per pass; the chosen shape is written to shape[6] (nullable) in the layout
- * of fft_homog_get_launch_shape.  The candidates are the x-pass block heights that fit the
- * default 64 KiB per-block LDS limit, with and without register staging, and 1..16 (y) or 1..8 (outer)
- * kx bins per block.  The CG work vectors are overwritten; the strain state, the material
- * and the last tangent's inputs are kept, so it may be called between any two calls.
- * Results of later solves agree with those of the default shape to rounding (the block
- * height changes the order of the partial sums). */
-int fft_homog_autotune(fft_homog_t* h, int reps, int shape[6]);
+/* Set the launch shape (layout of fft_homog_get_launch_shape), e.g. one that
+ * fft_homog_autotune chose for another handle of the same grid and batch.  EINVAL, with
+ * nothing changed, unless: the pitch is nx/2+1 or its default padding; 1 <= shape[0] <= 16 and
+ * <= ny*nz; 1 <= shape[1], shape[2] <= nx/2+1; register staging only where the FFT plan allows
+ * it; every pass within 64 KiB of LDS (or the shape create chose).  Takes effect from the next
+ * call; results agree with other shapes to rounding. */
+int fft_homog_set_launch_shape(fft_homog_t* h, const int shape[7]);
+
+/* Time every candidate launch shape of the CG passes on this handle's grid (each pass over
+ * `reps` launches after one warm-up, HIP events on the handle's stream, over as many
+ * right-hand sides of the batch as make up 4 Mi voxels) and keep the fastest; the chosen
+ * shape is written to shape[7] (nullable) in the layout of fft_homog_get_launch_shape.
+ * Candidates: both row pitches of the half spectrum; per pitch, x-pass block heights 1..16
+ * and 1..32 kx bins per y- and outer-pass block, each with and without register staging,
+ * within the default 64 KiB per-block LDS limit; a candidate must beat the default by 2 %.
+ * The CG work vectors are overwritten; the strain state, the material and the last tangent's
+ * inputs are kept, so it may be called between any two calls.  Results of later solves agree
+ * with those of the default shape to rounding (the block height changes the order of the
+ * partial sums). */
+int fft_homog_autotune(fft_homog_t* h, int reps, int shape[7]);
 
 void fft_homog_destroy(fft_homog_t* h);
 const char* fft_homog_strerror(int status);

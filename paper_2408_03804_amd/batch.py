@@ -92,7 +92,12 @@ class TangentBatcher:
                 table = np.stack([np.asarray(cells[i]["table"], dtype=np.float64) for i in chunk])
                 h.set_material(phase, table)
                 if self._tune is not None:
-                    self.shapes[self._tune] = h.autotune()
+                    # one tuning per grid shape; later chunk sizes of that grid reuse it
+                    known = [v for k, v in self.shapes.items() if k[0] == self._tune[0]]
+                    if known:
+                        h.set_launch_shape(known[0])
+                    else:
+                        self.shapes[self._tune] = h.autotune()
                 if h.cells == 1:
                     # a one-cell handle takes its tangent at a converged state: the reference
                     # state is one (zero load, no CG)

@@ -79,7 +79,7 @@ EXPORTS = [
     "fft_homog_destroy", "fft_homog_strerror", "fft_homog_last_error",
     "fft_homog_debug_constitutive", "fft_homog_debug_rfft", "fft_homog_debug_irfft",
     "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_time_cg",
-    "fft_homog_get_launch_shape", "fft_homog_autotune",
+    "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune",
 ]
 
 _lib = None
@@ -118,6 +118,7 @@ def load_library(path=LIB_PATH):
         "fft_homog_debug_apply_operator": (I, [P, P, P, I]),
         "fft_homog_debug_time_cg": (I, [P, I, DP]),
         "fft_homog_get_launch_shape": (I, [P, ctypes.POINTER(I)]),
+        "fft_homog_set_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_autotune": (I, [P, I, ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
@@ -136,7 +137,8 @@ class FFTHomogError(RuntimeError):
 
 
 def _shape_dict(s):
-    return {"x_rows": s[0], "y_bins": s[1], "outer_bins": s[2], "x_regs": s[3], "y_regs": s[4], "outer_regs": s[5]}
+    return {"x_rows": s[0], "y_bins": s[1], "outer_bins": s[2], "x_regs": s[3], "y_regs": s[4], "outer_regs": s[5],
+            "spectrum_pitch": s[6]}
 
 
 def _dptr(a):
@@ -265,12 +267,17 @@ class FFTHomog:
         return (C[0] if self.cells == 1 else C), st.as_dict()
 
     def launch_shape(self):
-        s = (ctypes.c_int * 6)()
+        s = (ctypes.c_int * 7)()
         self._check(self.L.fft_homog_get_launch_shape(self.h, s))
         return _shape_dict(s)
 
+    def set_launch_shape(self, shape):
+        keys = ["x_rows", "y_bins", "outer_bins", "x_regs", "y_regs", "outer_regs", "spectrum_pitch"]
+        s = (ctypes.c_int * 7)(*[int(shape[k]) for k in keys])
+        self._check(self.L.fft_homog_set_launch_shape(self.h, s))
+
     def autotune(self, reps=10):
-        s = (ctypes.c_int * 6)()
+        s = (ctypes.c_int * 7)()
         self._check(self.L.fft_homog_autotune(self.h, int(reps), s))
         return _shape_dict(s)
 

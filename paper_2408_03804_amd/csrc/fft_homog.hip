@@ -485,6 +485,39 @@ int reduce_to_host(fft_homog_t* h, int nslots, int nblocks) {
   return FFT_HOMOG_OK;
 }
 
+// Apply a launch shape (the layout of fft_homog_get_launch_shape) after checking that every
+// pass fits what its kernel assumes; returns EINVAL and changes nothing otherwise.
+int apply_shape(fft_homog_t* h, const int* s) {
+  const Geom& g = h->g;
+  const int rows = g.ny * g.nz;
+  const int R = s[0], TXm = s[1], TXo = s[2], ix = s[3], im = s[4], io = s[5], pitch = s[6];
+  const int pad = g.nxh >= 8 ? (g.nxh + 7) / 8 * 8 : g.nxh;
+  if (pitch != g.nxh && pitch != pad) return FFT_HOMOG_EINVAL;
+  if (R < 1 || R > 16 || R > rows || TXm < 1 || TXm > g.nxh || TXo < 1 || TXo > g.nxh) return FFT_HOMOG_EINVAL;
+  if ((ix != 0 && ix != 1) || (im != 0 && im != 1) || (io != 0 && io != 1)) return FFT_HOMOG_EINVAL;
+  if (ix && !inplace_ok(h->plan[0], (g.c * R + 1) / 2)) return FFT_HOMOG_EINVAL;
+  if (g.ndim == 3 && im && !inplace_ok(h->plan[1], TXm)) return FFT_HOMOG_EINVAL;
+  if (io && !inplace_ok(h->plan[g.ndim - 1], outer_group(g) * TXo)) return FFT_HOMOG_EINVAL;
+  const size_t lim = 64 * 1024;
+  if (std::max(xfwd_smem(g, R, ix), xinv_smem(g, R, ix)) > lim && !(R == h->L.R && ix == h->L.in_x))
+    return FFT_HOMOG_EINVAL;
+  if (g.ndim == 3 && mid_smem(g, TXm, im) > lim && !(TXm == h->L.TXm && im == h->L.in_m)) return FFT_HOMOG_EINVAL;
+  if (outer_smem(g, TXo, io) > lim && !(TXo == h->L.TXo && io == h->L.in_o)) return FFT_HOMOG_EINVAL;
+  drop_graphs(h);
+  h->g.nxp = pitch;
+  h->g.Nh = (long long)pitch * g.ny * g.nz;
+  h->L.R = R;
+  h->L.in_x = ix;
+  h->L.nblk_x = (rows + R - 1) / R;
+  if (g.ndim == 3) {
+    h->L.TXm = TXm;
+    h->L.in_m = im;
+  }
+  h->L.TXo = TXo;
+  h->L.in_o = io;
+  return FFT_HOMOG_OK;
+}
+
 // Average device time (ms) of `reps` launches of `body` after one untimed launch.
 template <class Body>
 hipError_t time_launches(fft_homog_t* h, int reps, Body body, double* ms) {
@@ -1040,8 +1073,9 @@ int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
   return FFT_HOMOG_OK;
 }
 
-int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[6]) {
+int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[7]) {
   if (!h || !shape) return FFT_HOMOG_EINVAL;
+  shape[6] = h->g.nxp;
   shape[0] = h->L.R;
   shape[1] = h->L.TXm;
   shape[2] = h->L.TXo;
@@ -1051,9 +1085,15 @@ int fft_homog_get_launch_shape(const fft_homog_t* h, int shape[6]) {
   return FFT_HOMOG_OK;
 }
 
+int fft_homog_set_launch_shape(fft_homog_t* h, const int* shape) {
+  if (!h || !shape) return fail(h, FFT_HOMOG_EINVAL, "null argument");
+  if (apply_shape(h, shape)) return fail(h, FFT_HOMOG_EINVAL, "launch shape does not fit this grid");
+  return FFT_HOMOG_OK;
+}
+
 int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
   if (!h || reps < 1) return fail(h, FFT_HOMOG_EINVAL, "bad arguments");
-  const Geom& g = h->g;
+  Geom& g = h->g;
   const int C = g.c;
   const int B = h->L.B;
   const int rows = g.ny * g.nz;
@@ -1064,97 +1104,122 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
   // candidates stay within the default per-block LDS limit (more would cut the blocks
   // per CU to two or one); the incumbent is always timed
   const size_t kLdsTune = 64 * 1024;
+  // right-hand sides timed: enough voxels (4 Mi) to fill the GPU, not the whole batch
+  const int Bt = (int)std::max(1LL, std::min((long long)B, (1LL << 22) / g.N));
   drop_graphs(h);
   // work vectors at zero, every right-hand side running with alpha = beta = 0: the passes
   // then do all their loads, stores and arithmetic while the state stays put (no reduction
   // runs, so nothing can stop the solve)
-  const size_t vec = (size_t)B * C * g.N * sizeof(double);
+  const size_t vec = (size_t)Bt * C * g.N * sizeof(double);
   FH_CK(hipMemsetAsync(h->x, 0, vec, h->stream));
   FH_CK(hipMemsetAsync(h->r, 0, vec, h->stream));
   FH_CK(hipMemsetAsync(h->p, 0, vec, h->stream));
-  int rc = upload_states(h, B);
+  int rc = upload_states(h, Bt);
   if (rc) return rc;
   if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, g, h->stream));
   const int prod = h->kst ? PROD_CGOP_STORED : PROD_CGOP;
 
-  // x passes: block height and register staging (forward and inverse together)
-  {
-    int best_r = h->L.R, best_ip = h->L.in_x;
-    double best = 0.0;
-    const int rmax = std::min(16, rows);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int r = rmax; r >= 1; --r)
-        for (int ip = 1; ip >= 0; --ip) {
-          const bool incumbent = (r == h->L.R && ip == h->L.in_x);
-          if ((pass == 0) != incumbent) continue;  // time the incumbent first
-          if (ip && !inplace_ok(h->plan[0], (C * r + 1) / 2)) continue;
-          if (!incumbent && std::max(xfwd_smem(g, r, ip), xinv_smem(g, r, ip)) > kLdsTune) continue;
-          XFwdArgs a = xfwd_args(h);
-          a.in = h->r;
-          a.p = h->p;
-          a.R = r;
-          a.nblocks = (rows + r - 1) / r;
-          a.inplace = ip;
-          XInvArgs ai = xinv_args(h);
-          ai.R = r;
-          ai.nblocks = a.nblocks;
-          ai.inplace = ip;
-          double ms = 0.0;
-          FH_CK(time_launches(h, reps, [&]() {
-            hipError_t e = launch_xfwd(prod, h->matcode, a, B, h->stream);
-            return e == hipSuccess ? launch_xinv(CONS_CGUPD, ai, B, h->stream) : e;
-          }, &ms));
-          if (incumbent) best = ms;
-          else if (ms < kGain * best) { best = ms; best_r = r; best_ip = ip; }
-        }
-    h->L.R = best_r;
-    h->L.in_x = best_ip;
-    h->L.nblk_x = (rows + best_r - 1) / best_r;
+  // The spectrum row pitch is tuned with the rest: the default pads rows to 8 bins (whole
+  // 128-byte lines for the y and outer tiles); unpadded rows move fewer bytes, which pays on
+  // small grids where the padding is a large share.  Per pitch, each pass is tuned on its own.
+  struct Shape { int nxp, R, in_x, TXm, in_m, TXo, in_o; double t; };
+  const Shape def{g.nxp, h->L.R, h->L.in_x, h->L.TXm, h->L.in_m, h->L.TXo, h->L.in_o, 0.0};
+  Shape best = def;
+  bool have_best = false;
+  const int pitches[2] = {def.nxp, g.nxh};
+  for (int pi = 0; pi < 2; ++pi) {
+    if (pi == 1 && pitches[1] == pitches[0]) break;
+    g.nxp = pitches[pi];
+    g.Nh = (long long)g.nxp * g.ny * g.nz;
+    Shape cur = def;
+    cur.nxp = g.nxp;
+    double total = 0.0;
+    // x passes: block height and register staging (forward and inverse together)
+    {
+      double bt = 0.0;
+      const int rmax = std::min(16, rows);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int r = rmax; r >= 1; --r)
+          for (int ip = 1; ip >= 0; --ip) {
+            const bool incumbent = (r == def.R && ip == def.in_x);
+            if ((pass == 0) != incumbent) continue;  // time the incumbent first
+            if (ip && !inplace_ok(h->plan[0], (C * r + 1) / 2)) continue;
+            if (!incumbent && std::max(xfwd_smem(g, r, ip), xinv_smem(g, r, ip)) > kLdsTune) continue;
+            XFwdArgs a = xfwd_args(h);
+            a.in = h->r;
+            a.p = h->p;
+            a.R = r;
+            a.nblocks = (rows + r - 1) / r;
+            a.inplace = ip;
+            XInvArgs ai = xinv_args(h);
+            ai.R = r;
+            ai.nblocks = a.nblocks;
+            ai.inplace = ip;
+            double ms = 0.0;
+            FH_CK(time_launches(h, reps, [&]() {
+              hipError_t e = launch_xfwd(prod, h->matcode, a, Bt, h->stream);
+              return e == hipSuccess ? launch_xinv(CONS_CGUPD, ai, Bt, h->stream) : e;
+            }, &ms));
+            if (incumbent) bt = ms;
+            else if (ms < kGain * bt) { bt = ms; cur.R = r; cur.in_x = ip; }
+          }
+      total += bt;
+    }
+    // y passes (3D): kx bins per block, forward and inverse together
+    if (g.ndim == 3) {
+      double bt = 0.0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int t = std::min(32, g.nxh); t >= 1; --t)
+          for (int ip = 1; ip >= 0; --ip) {
+            const bool incumbent = (t == def.TXm && ip == def.in_m);
+            if ((pass == 0) != incumbent) continue;
+            if (ip && !inplace_ok(h->plan[1], t)) continue;
+            if (!incumbent && mid_smem(g, t, ip) > kLdsTune) continue;
+            const AxisArgs a = axis_args(h, 1, t, h->st, ip);
+            double ms = 0.0;
+            FH_CK(time_launches(h, reps, [&]() {
+              hipError_t e = launch_mid(-1, a, Bt, h->stream);
+              return e == hipSuccess ? launch_mid(1, a, Bt, h->stream) : e;
+            }, &ms));
+            if (incumbent) bt = ms;
+            else if (ms < kGain * bt) { bt = ms; cur.TXm = t; cur.in_m = ip; }
+          }
+      total += bt;
+    }
+    // outer pass: kx bins per block
+    {
+      const int G = outer_group(g);
+      double bt = 0.0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int t = std::min(32, g.nxh); t >= 1; --t)
+          for (int ip = 1; ip >= 0; --ip) {
+            const bool incumbent = (t == def.TXo && ip == def.in_o);
+            if ((pass == 0) != incumbent) continue;
+            if (ip && !inplace_ok(pouter, G * t)) continue;
+            if (!incumbent && outer_smem(g, t, ip) > kLdsTune) continue;
+            const AxisArgs a = axis_args(h, g.ndim - 1, t, h->st, ip);
+            double ms = 0.0;
+            FH_CK(time_launches(h, reps, [&]() { return launch_outer(OUTER_PROJECT, a, Bt, h->stream); }, &ms));
+            if (incumbent) bt = ms;
+            else if (ms < kGain * bt) { bt = ms; cur.TXo = t; cur.in_o = ip; }
+          }
+      total += bt;
+    }
+    cur.t = total;
+    if (!have_best || total < kGain * best.t) {
+      best = cur;
+      have_best = true;
+    }
   }
-  // y passes (3D): kx bins per block, forward and inverse together
-  if (g.ndim == 3) {
-    int best_t = h->L.TXm, best_ip = h->L.in_m;
-    double best = 0.0;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int t = std::min(16, g.nxh); t >= 1; --t)
-        for (int ip = 1; ip >= 0; --ip) {
-          const bool incumbent = (t == h->L.TXm && ip == h->L.in_m);
-          if ((pass == 0) != incumbent) continue;
-          if (ip && !inplace_ok(h->plan[1], t)) continue;
-          if (!incumbent && mid_smem(g, t, ip) > kLdsTune) continue;
-          const AxisArgs a = axis_args(h, 1, t, h->st, ip);
-          double ms = 0.0;
-          FH_CK(time_launches(h, reps, [&]() {
-            hipError_t e = launch_mid(-1, a, B, h->stream);
-            return e == hipSuccess ? launch_mid(1, a, B, h->stream) : e;
-          }, &ms));
-          if (incumbent) best = ms;
-          else if (ms < kGain * best) { best = ms; best_t = t; best_ip = ip; }
-        }
-    h->L.TXm = best_t;
-    h->L.in_m = best_ip;
-  }
-  // outer pass: kx bins per block
-  {
-    const int G = outer_group(g);
-    int best_t = h->L.TXo, best_ip = h->L.in_o;
-    double best = 0.0;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int t = std::min(8, g.nxh); t >= 1; --t)
-        for (int ip = 1; ip >= 0; --ip) {
-          const bool incumbent = (t == h->L.TXo && ip == h->L.in_o);
-          if ((pass == 0) != incumbent) continue;
-          if (ip && !inplace_ok(pouter, G * t)) continue;
-          if (!incumbent && outer_smem(g, t, ip) > kLdsTune) continue;
-          const AxisArgs a = axis_args(h, g.ndim - 1, t, h->st, ip);
-          double ms = 0.0;
-          FH_CK(time_launches(h, reps, [&]() { return launch_outer(OUTER_PROJECT, a, B, h->stream); }, &ms));
-          if (incumbent) best = ms;
-          else if (ms < kGain * best) { best = ms; best_t = t; best_ip = ip; }
-        }
-    h->L.TXo = best_t;
-    h->L.in_o = best_ip;
-  }
+  g.nxp = best.nxp;
+  g.Nh = (long long)g.nxp * g.ny * g.nz;
+  h->L.R = best.R;
+  h->L.in_x = best.in_x;
+  h->L.nblk_x = (rows + best.R - 1) / best.R;
+  h->L.TXm = best.TXm;
+  h->L.in_m = best.in_m;
+  h->L.TXo = best.TXo;
+  h->L.in_o = best.in_o;
   h->L.smem_max = std::max(std::max(xfwd_smem(g, h->L.R, h->L.in_x), xinv_smem(g, h->L.R, h->L.in_x)),
                            std::max(mid_smem(g, h->L.TXm, h->L.in_m), outer_smem(g, h->L.TXo, h->L.in_o)));
   if (shape) fft_homog_get_launch_shape(h, shape);

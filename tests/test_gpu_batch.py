@@ -146,7 +146,9 @@ def test_autotuned_shape_keeps_oracle_parity(shape, kin, mat):
     default = h.launch_shape()
     tuned = h.autotune(reps=3)
     assert tuned == h.launch_shape()
-    assert 1 <= tuned["x_rows"] <= 16 and 1 <= tuned["outer_bins"] <= 8
+    nxh = shape[-1] // 2 + 1
+    assert 1 <= tuned["x_rows"] <= 16 and 1 <= tuned["outer_bins"] <= min(32, nxh)
+    assert tuned["spectrum_pitch"] in (nxh, (nxh + 7) // 8 * 8)
     if d == 2:
         assert tuned["y_bins"] == default["y_bins"]
     S, psi, st = h.solve(macro, 2)
@@ -179,3 +181,39 @@ def test_batcher_groups_uneven_sizes():
         Ci, _ = one_cell_tangent(shape, "small", "linear_elastic", cell["phase"], cell["table"], tol_cg=1e-10)
         assert np.abs(C[i] - Ci).max() < 1e-9 * np.abs(Ci).max(), i
     b.close()
+
+
+@pytest.mark.parametrize("shape,kin,mat", [((20, 18, 16), "finite", "neo_hookean"),
+                                           ((33, 28), "small", "linear_elastic"),
+                                           ((12, 10, 32), "small", "linear_elastic")])
+def test_explicit_launch_shapes_keep_oracle_parity(shape, kin, mat):
+    from paper_2408_03804_amd.binding import FFTHomogError
+    d = len(shape)
+    nxh = shape[-1] // 2 + 1
+    phase = workloads.grf_two_phase(shape, 3.0, 0.3, 9)
+    table = np.array([[2.0, 1.0], [40.0, 20.0]]) if kin == "finite" else np.array(
+        [workloads.lame(1.0, 0.3), workloads.lame(10.0, 0.3)])
+    macro = np.diag([1.02] + [1.0] * (d - 1)).reshape(-1) if kin == "finite" else np.r_[0.01, np.zeros(
+        2 if d == 2 else 5)]
+    lam, mu = lame_fields(phase, table)
+    prob = newton_cg.Problem(shape, mat, lam, mu)
+    ref = newton_cg.solve(prob, macro, n_increments=1, tol_cg=1e-12)
+    Sref = newton_cg.tensor_to_components(newton_cg.homogenized(prob.stress(ref["state"].field)), kin, d)
+    default = make(shape, kin, mat).launch_shape()
+    shapes = [dict(default, spectrum_pitch=nxh),
+              dict(default, x_rows=1, x_regs=0, y_bins=1, y_regs=0, outer_bins=nxh, outer_regs=0, spectrum_pitch=nxh)]
+    for sh in shapes:
+        h = make(shape, kin, mat, tol_cg=1e-12)
+        h.set_material(phase, table)
+        h.set_launch_shape(sh)
+        assert h.launch_shape()["spectrum_pitch"] == nxh
+        S, psi, st = h.solve(macro, 1)
+        assert st["status"] == "ok"
+        assert np.abs(S - Sref).max() < TOL_HOMOG * np.abs(Sref).max(), sh
+    h = make(shape, kin, mat)
+    pad = (nxh + 7) // 8 * 8
+    for bad in (dict(default, spectrum_pitch=pad + 1), dict(default, x_rows=17), dict(default, outer_bins=nxh + 1)):
+        with pytest.raises(FFTHomogError) as ei:
+            h.set_launch_shape(bad)
+        assert ei.value.status == "einval"
+    assert h.launch_shape() == default

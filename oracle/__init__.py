@@ -22,9 +22,12 @@ newton_cg    Newton-CG solve, homogenized stress/energy and homogenized tangent
 bruteforce   dense displacement-formulation solve for tiny grids (independent of G and CG)
 closed_forms isotropic stiffness, exact laminate, Voigt/Reuss bounds
 adjoint      gradient of homogenized energy/stress w.r.t. a per-voxel SIMP density
+plasticity   J2 return mapping, consistent tangent and history (Appendix B), the RVE problem
+surrogate    forward pass, loss gradient and Adam step of the stiffness surrogate network
 
 Parity status: every function above is pinned by the CPU tests in
-``tests/test_oracle_pins.py``; none is "parity unpinned".
+``tests/test_oracle_pins.py``, ``tests/test_oracle_plasticity.py`` and
+``tests/test_oracle_surrogate.py``; none is "parity unpinned".
 """
 
-from . import spectral, materials, newton_cg, bruteforce, closed_forms, adjoint  # noqa: F401
+from . import spectral, materials, newton_cg, bruteforce, closed_forms, adjoint, plasticity, surrogate  # noqa: F401

@@ -175,6 +175,10 @@ def solve(problem, macro, n_increments=1, tol_newton=1e-10, tol_cg=1e-10, max_ne
     status = "ok"
     prev = start
     for n in range(1, n_increments + 1):
+        # history-dependent laws (J2 plasticity) carry the converged state of the previous
+        # load step into this one (Appendix B: the trial state starts from eps_elas(t))
+        if getattr(problem, "pending", False):
+            problem.commit(field)
         current = start + (float(n) / float(n_increments)) * (target - start)
         field += current - prev
         prev = current
@@ -203,6 +207,8 @@ def solve(problem, macro, n_increments=1, tol_newton=1e-10, tol_cg=1e-10, max_ne
         newton_total += it
         if status != "ok":
             break
+        if hasattr(problem, "commit"):
+            problem.pending = True
 
     out_state = State(field, prev)
     result = {

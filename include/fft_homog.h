@@ -56,8 +56,17 @@ enum { FFT_HOMOG_SMALL_STRAIN = 0, FFT_HOMOG_FINITE_STRAIN = 1 };
  *   LINEAR_ELASTIC (small strain)   psi = lam/2 tr(eps)^2 + mu eps:eps
  *   NEO_HOOKEAN    (finite strain)  psi = mu/2 (tr(F^T F) - 3) - mu ln J + lam/2 (ln J)^2
  *   STVK           (finite strain)  psi = lam/2 tr(E)^2 + mu E:E,  E = (F^T F - I)/2
+ *   J2_PLASTIC     (small strain)   von Mises plasticity with linear isotropic hardening
+ *                                   (section 4.1.2, Appendix B): per phase lam, mu, yield
+ *                                   stress sig_y and hardening modulus H; the stress is the
+ *                                   predictor-corrector return mapping from the plastic
+ *                                   history of the last load step (flow direction
+ *                                   3/2 s/sig_eq), K : d_eps its forward-mode derivative.
+ *                                   The history of a converged load step is committed when
+ *                                   the next load step starts; the energy output is the
+ *                                   stored elastic energy.
  * 2D is plane strain (eps_33 = 0, F_33 = 1). */
-enum { FFT_HOMOG_LINEAR_ELASTIC = 0, FFT_HOMOG_NEO_HOOKEAN = 1, FFT_HOMOG_STVK = 2 };
+enum { FFT_HOMOG_LINEAR_ELASTIC = 0, FFT_HOMOG_NEO_HOOKEAN = 1, FFT_HOMOG_STVK = 2, FFT_HOMOG_J2_PLASTIC = 3 };
 
 /* How the CG operator obtains K : p (section 3.2):
  *   RECOMPUTE  forward-over-forward dual-number JVP of the stress at every CG iteration
@@ -73,14 +82,16 @@ enum { FFT_HOMOG_K_RECOMPUTE = 0, FFT_HOMOG_K_STORED = 1 };
                                       HIP graph (built on first use, rebuilt after set_material or
                                       autotune); results are bitwise those of direct launches */
 
-enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_ENERGY = 2 };
+enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_ENERGY = 2,
+       FFT_HOMOG_FIELD_PLASTIC = 3 /* J2: cumulative plastic strain */ };
 
 typedef struct fft_homog_desc {
   int ndim;          /* 2 or 3 */
   int n[3];          /* grid points along x, y, z; each 1..1024 with prime factors <= 61 */
   double len[3];     /* cell edge lengths along x, y, z (> 0); wavevector xi = 2 pi k / len */
   int kinematics;    /* FFT_HOMOG_SMALL_STRAIN or FFT_HOMOG_FINITE_STRAIN */
-  int material;      /* FFT_HOMOG_LINEAR_ELASTIC (small) or NEO_HOOKEAN / STVK (finite) */
+  int material;      /* LINEAR_ELASTIC or J2_PLASTIC (small), NEO_HOOKEAN or STVK (finite); J2
+                        takes no FLAG_DENSITY and no batch > 1 */
   int nphase;        /* 1..256 */
   double tol_newton; /* Newton stop: ||dF||_2 / (sqrt(N) ||F-bar||_F) < tol_newton */
   double tol_cg;     /* CG stop: ||r|| <= tol_cg ||b|| */
@@ -132,7 +143,8 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
 /* Microstructure (the two-phase RVEs of section 4: per-phase Lame parameters).
  *   phase            device u8[N], layout [z][y][x]; copied into the workspace.
  *                    Multi-cell handle: u8[batch][N], the cells back to back.
- *   phase_lambda_mu  host f64[nphase][2] = (lam, mu) per phase.
+ *   phase_lambda_mu  host f64[nphase][2] = (lam, mu) per phase; J2_PLASTIC: f64[nphase][4] =
+ *                    (lam, mu, sig_y, H) with sig_y >= 0, H >= 0, 3 mu + H > 0.
  *                    Multi-cell handle: f64[batch][nphase][2], one table per cell.
  *   density          device f64[N] or NULL; when given (requires FLAG_DENSITY), lam and mu of
  *                    voxel v are scaled by density[v]^simp_p.
@@ -172,11 +184,13 @@ int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, d
 
 /* Copy a field of the current state to device memory dst:
  *   STRAIN / STRESS: f64[d*d][N], full row-major tensor components (small strain expanded from
- *                    the packed storage); ENERGY: f64[N]. */
+ *                    the packed storage); ENERGY: f64[N]; PLASTIC (J2 only, else EINVAL): f64[N]
+ *                    cumulative plastic strain of the current state. */
 int fft_homog_get_field(fft_homog_t* h, int which, double* dst);
 
 /* Restart from a given state: src device f64[d*d][N] full tensors, macro host f64[ncomp] the
- * macro load that state belongs to (its voxel average).  Small strain takes the symmetric part. */
+ * macro load that state belongs to (its voxel average).  Small strain takes the symmetric part.
+ * J2: the plastic history restarts virgin (zero). */
 int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro);
 
 /* Launch shape of the CG passes: shape[0] lines per x-pass block, shape[1] kx bins per

@@ -18,15 +18,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfft_homog.so")
 
 SMALL_STRAIN, FINITE_STRAIN = 0, 1
-LINEAR_ELASTIC, NEO_HOOKEAN, STVK = 0, 1, 2
+LINEAR_ELASTIC, NEO_HOOKEAN, STVK, J2_PLASTIC = 0, 1, 2, 3
 K_RECOMPUTE, K_STORED = 0, 1
 FLAG_TANGENT, FLAG_DENSITY, FLAG_GRAPH = 1, 2, 4
-FIELD_STRAIN, FIELD_STRESS, FIELD_ENERGY = 0, 1, 2
+FIELD_STRAIN, FIELD_STRESS, FIELD_ENERGY, FIELD_PLASTIC = 0, 1, 2, 3
 MAX_RECORDED = 256
 
 STATUS = {0: "ok", 1: "einval", 2: "enotconv", 3: "edomain", 4: "ebreakdown", 5: "estate",
           6: "eunsupported", 7: "edevice", 8: "eworkspace"}
-MATERIALS = {"linear_elastic": LINEAR_ELASTIC, "neo_hookean": NEO_HOOKEAN, "stvk": STVK}
+MATERIALS = {"linear_elastic": LINEAR_ELASTIC, "neo_hookean": NEO_HOOKEAN, "stvk": STVK, "j2_plastic": J2_PLASTIC}
 
 
 class Desc(ctypes.Structure):
@@ -240,7 +240,7 @@ class FFTHomog:
         ph = self._dev(phase, self.torch.uint8)
         assert ph.numel() == self.N * self.cells
         tab = np.ascontiguousarray(table, dtype=np.float64)
-        assert tab.size == 2 * self.desc.nphase * self.cells
+        assert tab.size == (4 if self.desc.material == J2_PLASTIC else 2) * self.desc.nphase * self.cells
         den = None if density is None else self._dev(density, self.torch.float64)
         self._keep = (ph, den)
         rc = self.L.fft_homog_set_material(self.h, _tptr(ph), _dptr(tab),
@@ -302,7 +302,7 @@ class FFTHomog:
 
     def get_field(self, which):
         d = self.ndim
-        shape = self.shape if which == FIELD_ENERGY else (d, d) + self.shape
+        shape = self.shape if which in (FIELD_ENERGY, FIELD_PLASTIC) else (d, d) + self.shape
         out = self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
         self._check(self.L.fft_homog_get_field(self.h, int(which), _tptr(out)))
         return out

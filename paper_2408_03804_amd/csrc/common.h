@@ -60,12 +60,18 @@ struct Geom {
   int small;     // small strain (Mandel packing) or finite strain
 };
 
-// Per-voxel Lame parameters: (lam, mu) = table[phase[v]] * scale[v], where
-// scale = density^p is precomputed once per set_material (nullable: 1).
+// Per-voxel material parameters: row table[tstride * phase[v]] holds (lam, mu) and,
+// for J2 plasticity, (sig_y, H); lam and mu are multiplied by scale[v] = density^p,
+// precomputed once per set_material (nullable: 1).  J2 also reads the plastic history
+// of the voxel: hist[k * hN + v], k < c (packed plastic strain) and k = c (cumulative
+// plastic strain).
 struct MatParams {
   const uint8_t* phase;
-  const double* table;    // [nphase][2]
+  const double* table;    // [nphase][tstride]
   const double* scale;    // nullable
+  const double* hist;     // J2 only: [c + 1][N]
+  long long hN;           // voxels (history stride)
+  int tstride;            // 2, or 4 for J2
 };
 
 // CG bookkeeping of one right-hand side, kept on the device so alpha and beta

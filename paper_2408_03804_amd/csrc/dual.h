@@ -134,6 +134,23 @@ __host__ __device__ inline Dual<T, K> operator-(double s, const Dual<T, K>& a) {
 }
 
 // ---- elementary functions ---------------------------------------------------
+// value part at the innermost level (branch decisions are taken on it)
+__host__ __device__ inline double val(double a) { return a; }
+template <class T, int K>
+__host__ __device__ inline double val(const Dual<T, K>& a) { return val(a.v); }
+
+__host__ __device__ inline double dsqrt(double a) { return sqrt(a); }
+
+template <class T, int K>
+__host__ __device__ inline Dual<T, K> dsqrt(const Dual<T, K>& a) {
+  Dual<T, K> r;
+  r.v = dsqrt(a.v);
+  const T h = lift<T>(0.5) / r.v;
+#pragma unroll
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * h;
+  return r;
+}
+
 __host__ __device__ inline double dlog(double a) { return log(a); }
 
 template <class T, int K>

@@ -53,7 +53,8 @@ bool factorize(int n, int* radix, int* nst) {
 }
 
 struct Layout {
-  size_t F, x, r, p, spec, kst, phase, density, scale, table, tw[3], partials, state, active, results, flags, total;
+  size_t F, x, r, p, spec, kst, phase, density, scale, table, hist, tw[3], partials, state, active, results, flags,
+      total;
   int cells;  // independent cells (microstructures) of this grid held by the handle
   int B, R, TXm, TXo, nblk_x, nblk_vox;
   size_t n_results;
@@ -88,7 +89,11 @@ int validate_desc(const fft_homog_desc* d) {
     if (d->n[a] > kMaxAxis) return FFT_HOMOG_EUNSUPPORTED;
   }
   if (d->kinematics != FFT_HOMOG_SMALL_STRAIN && d->kinematics != FFT_HOMOG_FINITE_STRAIN) return FFT_HOMOG_EINVAL;
-  if (d->kinematics == FFT_HOMOG_SMALL_STRAIN && d->material != FFT_HOMOG_LINEAR_ELASTIC) return FFT_HOMOG_EINVAL;
+  if (d->kinematics == FFT_HOMOG_SMALL_STRAIN && d->material != FFT_HOMOG_LINEAR_ELASTIC &&
+      d->material != FFT_HOMOG_J2_PLASTIC)
+    return FFT_HOMOG_EINVAL;
+  if (d->material == FFT_HOMOG_J2_PLASTIC && (d->batch > 1 || (d->flags & FFT_HOMOG_FLAG_DENSITY)))
+    return FFT_HOMOG_EINVAL;
   if (d->kinematics == FFT_HOMOG_FINITE_STRAIN && d->material != FFT_HOMOG_NEO_HOOKEAN &&
       d->material != FFT_HOMOG_STVK)
     return FFT_HOMOG_EINVAL;
@@ -195,7 +200,9 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->phase = take((size_t)L->cells * g.N);
   L->density = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
   L->scale = take((d->flags & FFT_HOMOG_FLAG_DENSITY) ? (size_t)g.N * sizeof(double) : 0);
-  L->table = take((size_t)L->cells * 2 * kMaxPhase * sizeof(double));
+  const bool j2 = d->material == FFT_HOMOG_J2_PLASTIC;
+  L->table = take((size_t)L->cells * (j2 ? 4 : 2) * kMaxPhase * sizeof(double));
+  L->hist = take(j2 ? (size_t)(C + 1) * g.N * sizeof(double) : 0);
   for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? (size_t)d->n[a] * sizeof(double2) : 0);
   // room for one partial per row, so that any x-pass block height fits (launch-shape tuning)
   size_t np = (size_t)L->B * rows;
@@ -221,7 +228,8 @@ struct fft_homog {
   int matcode;
   hipStream_t stream;
   char* ws;
-  double *F, *x, *r, *p, *kst, *partials, *results, *table, *density, *scale;
+  double *F, *x, *r, *p, *kst, *partials, *results, *table, *density, *scale, *hist;
+  bool j2_pending;  // J2: the last converged load step is not yet committed to the history
   double simp_p;
   double2* spec;
   uint8_t* phase;
@@ -584,9 +592,15 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   for (int k = 0; k < kMaxC; ++k) h->macro_cur[k] = 0.0;
   if (!h->g.small)
     for (int i = 0; i < d->ndim; ++i) h->macro_cur[i * d->ndim + i] = 1.0;
+  const bool j2 = d->material == FFT_HOMOG_J2_PLASTIC;
+  h->hist = j2 ? (double*)(h->ws + L.hist) : nullptr;
+  h->j2_pending = false;
   h->mat.phase = h->phase;
   h->mat.table = h->table;
   h->mat.scale = nullptr;
+  h->mat.hist = h->hist;
+  h->mat.hN = h->g.N;
+  h->mat.tstride = j2 ? 4 : 2;
   h->simp_p = 0.0;
   h->h_st = nullptr;
   h->ev0 = h->ev1 = nullptr;
@@ -629,7 +643,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
     e = hipMemcpyAsync(dtw, tw[a].data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream);
   }
   if (h->g.ndim == 2) h->plan[2] = h->plan[1];
-  std::vector<double> zeros((size_t)L.cells * 2 * kMaxPhase, 0.0);
+  std::vector<double> zeros((size_t)L.cells * (j2 ? 4 : 2) * kMaxPhase, 0.0);
   if (e == hipSuccess) {
     step = "phase table init";
     e = hipMemcpyAsync(h->table, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
@@ -641,6 +655,10 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   if (e == hipSuccess) {
     step = "reference strain";
     e = launch_init_reference(h->F, h->g, h->stream);
+  }
+  if (e == hipSuccess && j2) {
+    step = "plastic history init";
+    e = hipMemsetAsync(h->hist, 0, (size_t)(h->g.c + 1) * h->g.N * sizeof(double), h->stream);
   }
   if (e == hipSuccess) {
     step = "LDS limit";
@@ -664,13 +682,18 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
   if (!h || !phase || !lm) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   if (density && !h->density) return fail(h, FFT_HOMOG_EINVAL, "density given but FLAG_DENSITY not set");
   const int cells = h->L.cells;
-  const size_t row = 2 * (size_t)h->desc.nphase * sizeof(double);
-  for (long long k = 0; k < 2LL * h->desc.nphase * cells; ++k)
+  const int ts = h->mat.tstride;
+  const size_t row = (size_t)ts * h->desc.nphase * sizeof(double);
+  for (long long k = 0; k < (long long)ts * h->desc.nphase * cells; ++k)
     if (!std::isfinite(lm[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite phase table entry");
+  if (ts == 4)
+    for (int ph = 0; ph < h->desc.nphase; ++ph)
+      if (!(lm[4 * ph + 2] >= 0.0) || !(lm[4 * ph + 3] >= 0.0) || !(3.0 * lm[4 * ph + 1] + lm[4 * ph + 3] > 0.0))
+        return fail(h, FFT_HOMOG_EINVAL, "J2 phase needs sig_y >= 0, H >= 0, 3 mu + H > 0");
   drop_graphs(h);
   FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)cells * h->g.N, hipMemcpyDeviceToDevice, h->stream));
-  FH_CK(hipMemcpy2DAsync(h->table, 2 * kMaxPhase * sizeof(double), lm, row, row, cells, hipMemcpyHostToDevice,
-                         h->stream));
+  FH_CK(hipMemcpy2DAsync(h->table, (size_t)ts * kMaxPhase * sizeof(double), lm, row, row, cells,
+                         hipMemcpyHostToDevice, h->stream));
   if (density) {
     FH_CK(hipMemcpyAsync(h->density, density, (size_t)h->g.N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     FH_CK(launch_simp_scale(h->density, simp_p, h->scale, h->g.N, h->stream));
@@ -715,6 +738,11 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
       mn += cur[k] * cur[k];
     }
     mn = std::sqrt(mn);
+    if (h->j2_pending) {
+      // the previous load step converged: its plastic state becomes the history of this one
+      FH_CK(launch_j2_commit(h->matcode, h->F, h->mat, h->hist, h->g, h->stream));
+      h->j2_pending = false;
+    }
     FH_CK(launch_shift(h->F, delta, h->g, h->stream));
     for (int k = 0; k < C; ++k) h->macro_cur[k] = cur[k];
     int it = 0;
@@ -743,7 +771,10 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
       S.newton_residual = res;
       if (res < h->desc.tol_newton) break;
     }
-    if (status == FFT_HOMOG_OK) S.increments = n;
+    if (status == FFT_HOMOG_OK) {
+      S.increments = n;
+      if (h->hist) h->j2_pending = true;
+    }
   }
 
   if (status != FFT_HOMOG_EDOMAIN) {
@@ -824,6 +855,7 @@ int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, d
                       fft_homog_stats* stats) {
   if (!h || !w_stress || !grad_density) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
+  if (h->hist) return fail(h, FFT_HOMOG_EUNSUPPORTED, "no density gradient for J2 plasticity");
   if (!h->mat.scale) return fail(h, FFT_HOMOG_ESTATE, "no density field set (FLAG_DENSITY and set_material)");
   if (!h->solved_ok) return fail(h, FFT_HOMOG_ESTATE, "no converged solve");
   if (!std::isfinite(w_energy)) return fail(h, FFT_HOMOG_EINVAL, "non-finite weight");
@@ -883,6 +915,8 @@ int fft_homog_get_field(fft_homog_t* h, int which, double* dst) {
     FH_CK(launch_expand(h->r, dst, h->g, h->stream));
   } else if (which == FFT_HOMOG_FIELD_ENERGY) {
     FH_CK(launch_stress_field(h->matcode, h->F, h->mat, nullptr, dst, h->g, h->stream));
+  } else if (which == FFT_HOMOG_FIELD_PLASTIC && h->hist) {
+    FH_CK(launch_j2_plastic(h->matcode, h->F, h->mat, dst, h->g, h->stream));
   } else {
     return fail(h, FFT_HOMOG_EINVAL, "unknown field");
   }
@@ -894,6 +928,11 @@ int fft_homog_set_field(fft_homog_t* h, const double* src, const double* macro) 
   if (!h || !src || !macro) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
   FH_CK(launch_pack(src, h->F, h->g, h->stream));
+  if (h->hist) {
+    // a prescribed state starts with a virgin plastic history
+    FH_CK(hipMemsetAsync(h->hist, 0, (size_t)(h->g.c + 1) * h->g.N * sizeof(double), h->stream));
+    h->j2_pending = false;
+  }
   to_packed(h, macro, h->macro_cur);
   FH_CK(hipStreamSynchronize(h->stream));
   h->solved_ok = false;

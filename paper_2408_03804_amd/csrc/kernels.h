@@ -103,6 +103,10 @@ hipError_t launch_debug_constitutive(int mat, const double* e, const double* de,
 hipError_t launch_simp_gradient(int mat, const double* F, const double* x, MatParams m, const double* density,
                                 double p, const double* W, double w_energy, double* grad, const Geom& g,
                                 hipStream_t s);
+// J2 plasticity: commit the history at the converged strain F (in place), and the
+// cumulative plastic strain of the state at F
+hipError_t launch_j2_commit(int mat, const double* F, MatParams m, double* hist, const Geom& g, hipStream_t s);
+hipError_t launch_j2_plastic(int mat, const double* F, MatParams m, double* out, const Geom& g, hipStream_t s);
 hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes);
 
 }  // namespace fh

@@ -33,17 +33,29 @@ namespace fh {
     case 3: MACRO(MAT_NH, 3); break;    \
     case 4: MACRO(MAT_STVK, 2); break;  \
     case 5: MACRO(MAT_STVK, 3); break;  \
+    case 6: MACRO(MAT_J2, 2); break;    \
+    case 7: MACRO(MAT_J2, 3); break;    \
     default: return hipErrorInvalidValue; \
   }
 
-__device__ __forceinline__ void load_lame(const MatParams& m, long long v, double& lam, double& mu) {
+// Parameters (and for J2 the plastic history) of voxel v.
+template <int MAT, int NDIM>
+__device__ __forceinline__ void load_local(const MatParams& m, long long v, Local& L) {
   const int ph = m.phase[v];
-  lam = m.table[2 * ph];
-  mu = m.table[2 * ph + 1];
+  const double* row = m.table + (long long)m.tstride * ph;
+  L.lam = row[0];
+  L.mu = row[1];
   if (m.scale != nullptr) {
     const double s = m.scale[v];
-    lam *= s;
-    mu *= s;
+    L.lam *= s;
+    L.mu *= s;
+  }
+  if constexpr (MAT == MAT_J2) {
+    constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+    L.sy = row[2];
+    L.H = row[3];
+#pragma unroll
+    for (int k = 0; k <= C; ++k) L.hist[k] = m.hist[k * m.hN + v];
   }
 }
 
@@ -150,11 +162,10 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) E[j * nv + t] = ld_stream(a.F + j * N + vox);
       }
-      {
-        double lam, mu;
-        load_lame(mat, vox, lam, mu);  // brings the phase id and table line into cache
-        (void)lam;
-        (void)mu;
+      if (MAT != MAT_J2) {
+        Local L;
+        load_local<MAT, NDIM>(mat, vox, L);  // brings the phase id and table line into cache
+        (void)L;
       }
 #pragma unroll
       for (int j = 0; j < C; ++j) {
@@ -185,13 +196,13 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
       for (int j = 0; j < C; ++j) v[j] = a.in[((long long)b * C + j) * N + vox];
     } else {
-      double lam, mu;
+      Local L;
       double e[C];
       // the linear elastic energy is quadratic: K does not depend on the strain,
       // so the tangent passes do not read it
       // (lam, mu) are re-read here (cache hits): staging them in LDS as well
       // raises the register count of the fused kernel by a third
-      load_lame(mat, vox, lam, mu);
+      load_local<MAT, NDIM>(mat, vox, L);
       if (CGOP) {
 #pragma unroll
         for (int j = 0; j < C; ++j) e[j] = (PROD == PROD_CGOP && MAT != MAT_LE) ? E[j * nv + t] : 0.0;
@@ -201,11 +212,11 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
       }
       if (PROD == PROD_STRESS) {
-        if (MAT != MAT_LE) {
+        if (MAT == MAT_NH || MAT == MAT_STVK) {
           const double J = det_packed<NDIM>(e);
           if (!(J > 0.0)) bad = 1;
         }
-        stress_ad<MAT, NDIM>(e, lam, mu, v);
+        stress_ad<MAT, NDIM>(e, L, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           acc += v[j] * v[j];
@@ -216,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         double P[C], W[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) W[j] = a.unit[j];
-        stress_and_jvp_ad<MAT, NDIM>(e, W, lam, mu, P, v);
+        stress_and_jvp_ad<MAT, NDIM>(e, W, L, P, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           v[j] += a.w_energy * P[j];
@@ -226,7 +237,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         double de[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) de[j] = (j == lb) ? a.unit[lb] : 0.0;
-        tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, v);
+        tangent_jvp_ad<MAT, NDIM>(e, de, L, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) acc += v[j] * v[j];
       } else {  // CG operator: v = K : p with p from phase A
@@ -234,7 +245,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) pv[j] = *slot(j, r, x);
         if (PROD == PROD_CGOP) {
-          tangent_jvp_ad<MAT, NDIM>(e, pv, lam, mu, v);
+          tangent_jvp_ad<MAT, NDIM>(e, pv, L, v);
         } else {
           // stored symmetric tangent, upper triangle row by row
 #pragma unroll
@@ -730,12 +741,13 @@ __global__ void __launch_bounds__(kThreads) k_homogenize(const double* F, MatPar
 #pragma unroll
   for (int k = 0; k <= C; ++k) vals[k] = 0.0;
   if (v < N) {
-    double e[C], lam, mu;
+    double e[C];
+    Local L;
 #pragma unroll
     for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-    load_lame(m, v, lam, mu);
-    if (MAT != MAT_LE && !(det_packed<NDIM>(e) > 0.0)) st[0].domain = 1;
-    vals[C] = stress_ad<MAT, NDIM>(e, lam, mu, vals);
+    load_local<MAT, NDIM>(m, v, L);
+    if ((MAT == MAT_NH || MAT == MAT_STVK) && !(det_packed<NDIM>(e) > 0.0)) st[0].domain = 1;
+    vals[C] = stress_ad<MAT, NDIM>(e, L, vals);
   }
   block_sum_many(vals, C + 1, sh, partials, nblocks);
 }
@@ -752,16 +764,17 @@ __global__ void __launch_bounds__(kThreads) k_tangent_matrix(const double* F, co
 #pragma unroll
   for (int k = 0; k < C * C; ++k) vals[k] = 0.0;
   if (v < N) {
-    double e[C], lam, mu;
+    double e[C];
+    Local L;
     const bool need_e = MAT != MAT_LE;
 #pragma unroll
     for (int j = 0; j < C; ++j) e[j] = need_e ? F[j * N + v] : 0.0;
-    load_lame(m, v, lam, mu);
+    load_local<MAT, NDIM>(m, v, L);
     for (int J = 0; J < C; ++J) {
       double tJ[C], w[C];
 #pragma unroll
       for (int j = 0; j < C; ++j) tJ[j] = X[((long long)J * C + j) * N + v] + (j == J ? unit.v[J] : 0.0);
-      tangent_jvp_ad<MAT, NDIM>(e, tJ, lam, mu, w);
+      tangent_jvp_ad<MAT, NDIM>(e, tJ, L, w);
       for (int I = 0; I < C; ++I) {
         double s = 0.0;
 #pragma unroll
@@ -779,16 +792,17 @@ __global__ void __launch_bounds__(kThreads) k_store_tangent(const double* F, Mat
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
-  double e[C], lam, mu;
+  double e[C];
+  Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-  load_lame(m, v, lam, mu);
+  load_local<MAT, NDIM>(m, v, L);
   int idx = 0;
   for (int i = 0; i < C; ++i) {
     double de[C], col[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) de[j] = (j == i) ? 1.0 : 0.0;
-    tangent_jvp_ad<MAT, NDIM>(e, de, lam, mu, col);  // column i = row i (K symmetric)
+    tangent_jvp_ad<MAT, NDIM>(e, de, L, col);  // column i = row i (K symmetric)
     for (int j = i; j < C; ++j) {
       Kst[(long long)idx * N + v] = col[j];
       ++idx;
@@ -841,6 +855,39 @@ __global__ void k_pack(const double* full, double* packed, Geom g) {
   }
 }
 
+// J2: move the plastic history to the converged state at F (one load step ends)
+template <int NDIM>
+__global__ void __launch_bounds__(kThreads) k_j2_commit(const double* F, MatParams m, double* hist, Geom g) {
+  constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], h[C + 1];
+  Local L;
+#pragma unroll
+  for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+  load_local<MAT_J2, NDIM>(m, v, L);
+  j2_commit<NDIM>(e, L, h);
+#pragma unroll
+  for (int k = 0; k <= C; ++k) hist[k * N + v] = h[k];
+}
+
+// J2: cumulative plastic strain of the state at F (history plus this step's increment)
+template <int NDIM>
+__global__ void __launch_bounds__(kThreads) k_j2_plastic(const double* F, MatParams m, double* out, Geom g) {
+  constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  const long long N = g.N;
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double e[C], h[C + 1];
+  Local L;
+#pragma unroll
+  for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
+  load_local<MAT_J2, NDIM>(m, v, L);
+  j2_commit<NDIM>(e, L, h);
+  out[v] = h[C];
+}
+
 template <int MAT, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_stress_field(const double* F, MatParams m, double* packed_out,
                                                            double* energy_out, Geom g) {
@@ -848,11 +895,12 @@ __global__ void __launch_bounds__(kThreads) k_stress_field(const double* F, MatP
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
-  double e[C], P[C], lam, mu;
+  double e[C], P[C];
+  Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-  load_lame(m, v, lam, mu);
-  const double psi = stress_ad<MAT, NDIM>(e, lam, mu, P);
+  load_local<MAT, NDIM>(m, v, L);
+  const double psi = stress_ad<MAT, NDIM>(e, L, P);
   if (packed_out != nullptr) {
 #pragma unroll
     for (int j = 0; j < C; ++j) packed_out[j * N + v] = P[j];
@@ -870,11 +918,12 @@ __global__ void __launch_bounds__(kThreads) k_simp_gradient(const double* F, con
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
-  double e[C], P[C], lam, mu;
+  double e[C], P[C];
+  Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-  load_lame(m, v, lam, mu);
-  const double psi = stress_ad<MAT, NDIM>(e, lam, mu, P);
+  load_local<MAT, NDIM>(m, v, L);
+  const double psi = stress_ad<MAT, NDIM>(e, L, P);
   double wp = w_energy * psi;
 #pragma unroll
   for (int j = 0; j < C; ++j) wp += (W.v[j] + x[j * N + v]) * P[j];
@@ -899,14 +948,15 @@ __global__ void __launch_bounds__(kThreads) k_debug_constitutive(const double* e
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
-  double e[C], de[C], p[C], k[C], lam, mu;
+  double e[C], de[C], p[C], k[C];
+  Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     e[j] = e_in[j * N + v];
     de[j] = de_in[j * N + v];
   }
-  load_lame(m, v, lam, mu);
-  const double ps = stress_and_jvp_ad<MAT, NDIM>(e, de, lam, mu, p, k);
+  load_local<MAT, NDIM>(m, v, L);
+  const double ps = stress_and_jvp_ad<MAT, NDIM>(e, de, L, p, k);
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     P[j * N + v] = p[j];
@@ -1100,6 +1150,20 @@ hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipS
 
 hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, stride_grid(g.N), dim3(kThreads), 0, s, full, packed, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_j2_commit(int mat, const double* F, MatParams m, double* hist, const Geom& g, hipStream_t s) {
+  if (mat == 6) hipLaunchKernelGGL((k_j2_commit<2>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
+  else if (mat == 7) hipLaunchKernelGGL((k_j2_commit<3>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_j2_plastic(int mat, const double* F, MatParams m, double* out, const Geom& g, hipStream_t s) {
+  if (mat == 6) hipLaunchKernelGGL((k_j2_plastic<2>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
+  else if (mat == 7) hipLaunchKernelGGL((k_j2_plastic<3>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

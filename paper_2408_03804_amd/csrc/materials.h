@@ -15,16 +15,33 @@
 //   linear elastic      psi = lam/2 tr(eps)^2 + mu eps:eps
 //   Neo-Hookean         psi = mu/2 (tr(F^T F) - 3) - mu ln J + lam/2 (ln J)^2
 //   St.Venant-Kirchhoff psi = lam/2 tr(E)^2 + mu E:E,  E = (F^T F - I)/2
+//
+// J2 plasticity (small strain, linear isotropic hardening) has no energy whose
+// derivative is the stress: its stress is the predictor-corrector return mapping
+// of the paper's Appendix B, written once generically in the scalar type, and
+// K : d_e is the forward-mode derivative of that function along d_e (the paper's
+// jvp of its stress update).
 #pragma once
 
 #include "dual.h"
 
 namespace fh {
 
-enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2 };
+enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2, MAT_J2 = 3 };
+
+// Parameters and state of one voxel: Lame parameters, and for J2 the yield stress,
+// hardening modulus and plastic history (packed plastic strain, cumulative plastic strain)
+// of the last committed load step.
+struct Local {
+  double lam, mu;
+  double sy, H;
+  double hist[7];
+};
 
 template <int MAT, int NDIM>
 struct MatTraits;
+template <> struct MatTraits<MAT_J2, 2> { static constexpr int C = 3; };
+template <> struct MatTraits<MAT_J2, 3> { static constexpr int C = 6; };
 template <> struct MatTraits<MAT_LE, 2> { static constexpr int C = 3; };
 template <> struct MatTraits<MAT_LE, 3> { static constexpr int C = 6; };
 template <> struct MatTraits<MAT_NH, 2> { static constexpr int C = 4; };
@@ -106,101 +123,211 @@ struct Energy<MAT_STVK, 2, S> {
   }
 };
 
+// ---- J2 return mapping (generic in the scalar type) ---------------------------
+// Packed Mandel strain e (C components; 2D plane strain: [e11, e22, sqrt2 e12], e33 = 0).
+// Internally full 3D Mandel [11, 22, 33, sqrt2 23, sqrt2 13, sqrt2 12]; the plastic strain
+// is deviatoric, so in 2D its out-of-plane entry is -(ep11 + ep22).
+//   trial: ee = e - ep, sig = lam tr(ee) I + 2 mu ee, s = dev(sig), seq = sqrt(3/2 s:s)
+//   Phi = seq - (sy + H p); if Phi > 0: dp = Phi / (3 mu + H), N = 3/2 s / seq,
+//   sig -= 2 mu dp N  (N = 3/2 s / seq returns the stress onto the hardened yield surface)
+// The elastic / plastic branch is decided on the value; derivatives follow the branch.
+template <int NDIM, class T>
+__device__ inline void j2_return(const T* e, const Local& L, T* sig6, T& dp, T* N6, bool& plastic) {
+  T ee[6];
+  if (NDIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ee[k] = e[k] - L.hist[k];
+  } else {
+    ee[0] = e[0] - L.hist[0];
+    ee[1] = e[1] - L.hist[1];
+    ee[2] = lift<T>(L.hist[0] + L.hist[1]);  // 0 - ep33
+    ee[3] = lift<T>(0.0);
+    ee[4] = lift<T>(0.0);
+    ee[5] = e[2] - L.hist[2];
+  }
+  const double p = L.hist[NDIM == 3 ? 6 : 3];
+  const T tr = ee[0] + ee[1] + ee[2];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig6[k] = (2.0 * L.mu) * ee[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) sig6[k] = sig6[k] + L.lam * tr;
+  const T m = (sig6[0] + sig6[1] + sig6[2]) * (1.0 / 3.0);
+  T s[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = (k < 3) ? sig6[k] - m : sig6[k];
+  T ss = s[0] * s[0];
+#pragma unroll
+  for (int k = 1; k < 6; ++k) ss = ss + s[k] * s[k];
+  const double phi_v = sqrt(1.5 * val(ss)) - (L.sy + L.H * p);
+  plastic = phi_v > 0.0;
+  if (!plastic) {
+    dp = lift<T>(0.0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) N6[k] = lift<T>(0.0);
+    return;
+  }
+  const T seq = dsqrt(1.5 * ss);
+  dp = (seq - (L.sy + L.H * p)) * (1.0 / (3.0 * L.mu + L.H));
+  const T f = lift<T>(1.5) / seq;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    N6[k] = f * s[k];
+    sig6[k] = sig6[k] - (2.0 * L.mu) * (dp * N6[k]);
+  }
+}
+
+template <int NDIM, class T>
+__device__ inline void j2_pack(const T* sig6, T* out) {
+  if (NDIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k] = sig6[k];
+  } else {
+    out[0] = sig6[0];
+    out[1] = sig6[1];
+    out[2] = sig6[5];
+  }
+}
+
+// stored elastic energy 1/2 ee : C : ee of the returned state (the J2 "energy" output)
+template <int NDIM>
+__device__ inline double j2_energy(const double* e, const Local& L, const double* sig6) {
+  // ee = C^-1 sig: tr(ee) = tr(sig) / (3 lam + 2 mu), dev(ee) = dev(sig) / (2 mu)
+  const double trs = sig6[0] + sig6[1] + sig6[2];
+  const double tre = trs / (3.0 * L.lam + 2.0 * L.mu);
+  double w = 0.5 * trs * tre / 3.0;  // volumetric part 1/2 (tr sig / 3)(tr ee)
+  const double m = trs / 3.0;
+  double dd = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double s = (k < 3) ? sig6[k] - m : sig6[k];
+    dd += s * s;
+  }
+  return w + 0.25 * dd / L.mu;
+}
+
 // ---- derivatives by forward-mode AD -------------------------------------------
 
-// psi and its gradient (the stress) at e: one vector-dual pass.
+// psi and its gradient (the stress) at e: one vector-dual pass.  J2: the return-mapped
+// stress, and the stored elastic energy.
 template <int MAT, int NDIM>
-__device__ inline double stress_ad(const double* e, double lam, double mu, double* P) {
+__device__ inline double stress_ad(const double* e, const Local& L, double* P) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
-  Dual<double, C> x[C];
+  if constexpr (MAT == MAT_J2) {
+    double sig6[6], N6[6], dp;
+    bool pl;
+    j2_return<NDIM, double>(e, L, sig6, dp, N6, pl);
+    j2_pack<NDIM, double>(sig6, P);
+    return j2_energy<NDIM>(e, L, sig6);
+  } else {
+    Dual<double, C> x[C];
 #pragma unroll
-  for (int k = 0; k < C; ++k) {
-    x[k].v = e[k];
+    for (int k = 0; k < C; ++k) {
+      x[k].v = e[k];
 #pragma unroll
-    for (int j = 0; j < C; ++j) x[k].d[j] = (j == k) ? 1.0 : 0.0;
+      for (int j = 0; j < C; ++j) x[k].d[j] = (j == k) ? 1.0 : 0.0;
+    }
+    Dual<double, C> r = Energy<MAT, NDIM, Dual<double, C>>::psi(x, L.lam, L.mu);
+#pragma unroll
+    for (int k = 0; k < C; ++k) P[k] = r.d[k];
+    return r.v;
   }
-  Dual<double, C> r = Energy<MAT, NDIM, Dual<double, C>>::psi(x, lam, mu);
-#pragma unroll
-  for (int k = 0; k < C; ++k) P[k] = r.d[k];
-  return r.v;
 }
 
-// K(e) : de, the Jacobian-vector product of the stress, by forward over forward.
+// K(e) : de, the Jacobian-vector product of the stress, by forward over forward (J2:
+// one forward pass of the return mapping along de).
 template <int MAT, int NDIM>
-__device__ inline void tangent_jvp_ad(const double* e, const double* de, double lam, double mu,
-                                      double* out) {
+__device__ inline void tangent_jvp_ad(const double* e, const double* de, const Local& L, double* out) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
   typedef Dual<double, 1> T;
-  Dual<T, C> x[C];
+  if constexpr (MAT == MAT_J2) {
+    T x[C], sig6[6], N6[6], dp, o[C];
+    bool pl;
 #pragma unroll
-  for (int k = 0; k < C; ++k) {
-    x[k].v.v = e[k];
-    x[k].v.d[0] = de[k];
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      x[k].d[j].v = (j == k) ? 1.0 : 0.0;
-      x[k].d[j].d[0] = 0.0;
+    for (int k = 0; k < C; ++k) {
+      x[k].v = e[k];
+      x[k].d[0] = de[k];
     }
-  }
-  Dual<T, C> r = Energy<MAT, NDIM, Dual<T, C>>::psi(x, lam, mu);
+    j2_return<NDIM, T>(x, L, sig6, dp, N6, pl);
+    j2_pack<NDIM, T>(sig6, o);
 #pragma unroll
-  for (int k = 0; k < C; ++k) out[k] = r.d[k].d[0];
-}
-
-// Same product, one input direction at a time: for each k, a hyper-dual pass
-// seeded with e_k (outer level) and de (inner level) gives (K : de)_k as the
-// mixed second derivative of psi.  C cheap passes over 4-double numbers
-// instead of one pass over 2(C+1)-double numbers: fewer live registers.
-template <int MAT, int NDIM>
-__device__ inline void tangent_jvp_ad_dirs(const double* e, const double* de, double lam, double mu,
-                                           double* out) {
-  constexpr int C = MatTraits<MAT, NDIM>::C;
-  typedef Dual<double, 1> T;
-  typedef Dual<T, 1> S;
+    for (int k = 0; k < C; ++k) out[k] = o[k].d[0];
+  } else {
+    Dual<T, C> x[C];
 #pragma unroll
-  for (int k = 0; k < C; ++k) out[k] = 0.0;
-#pragma unroll 1
-  for (int k = 0; k < C; ++k) {
-    S x[C];
+    for (int k = 0; k < C; ++k) {
+      x[k].v.v = e[k];
+      x[k].v.d[0] = de[k];
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      x[j].v.v = e[j];
-      x[j].v.d[0] = de[j];
-      x[j].d[0].v = (j == k) ? 1.0 : 0.0;
-      x[j].d[0].d[0] = 0.0;
+      for (int j = 0; j < C; ++j) {
+        x[k].d[j].v = (j == k) ? 1.0 : 0.0;
+        x[k].d[j].d[0] = 0.0;
+      }
     }
-    const S r = Energy<MAT, NDIM, S>::psi(x, lam, mu);
-    const double val = r.d[0].d[0];
+    Dual<T, C> r = Energy<MAT, NDIM, Dual<T, C>>::psi(x, L.lam, L.mu);
 #pragma unroll
-    for (int j = 0; j < C; ++j)
-      if (j == k) out[j] = val;
+    for (int k = 0; k < C; ++k) out[k] = r.d[k].d[0];
   }
 }
 
 // Stress and K : de together (same nested pass; the stress is in the partials' values).
 template <int MAT, int NDIM>
-__device__ inline double stress_and_jvp_ad(const double* e, const double* de, double lam, double mu,
-                                           double* P, double* KdE) {
+__device__ inline double stress_and_jvp_ad(const double* e, const double* de, const Local& L, double* P,
+                                           double* KdE) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
   typedef Dual<double, 1> T;
-  Dual<T, C> x[C];
+  if constexpr (MAT == MAT_J2) {
+    T x[C], sig6[6], N6[6], dp, o[C];
+    bool pl;
 #pragma unroll
-  for (int k = 0; k < C; ++k) {
-    x[k].v.v = e[k];
-    x[k].v.d[0] = de[k];
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      x[k].d[j].v = (j == k) ? 1.0 : 0.0;
-      x[k].d[j].d[0] = 0.0;
+    for (int k = 0; k < C; ++k) {
+      x[k].v = e[k];
+      x[k].d[0] = de[k];
     }
-  }
-  Dual<T, C> r = Energy<MAT, NDIM, Dual<T, C>>::psi(x, lam, mu);
+    j2_return<NDIM, T>(x, L, sig6, dp, N6, pl);
+    j2_pack<NDIM, T>(sig6, o);
+    double s6[6];
 #pragma unroll
-  for (int k = 0; k < C; ++k) {
-    P[k] = r.d[k].v;
-    KdE[k] = r.d[k].d[0];
+    for (int k = 0; k < 6; ++k) s6[k] = sig6[k].v;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      P[k] = o[k].v;
+      KdE[k] = o[k].d[0];
+    }
+    return j2_energy<NDIM>(e, L, s6);
+  } else {
+    Dual<T, C> x[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      x[k].v.v = e[k];
+      x[k].v.d[0] = de[k];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        x[k].d[j].v = (j == k) ? 1.0 : 0.0;
+        x[k].d[j].d[0] = 0.0;
+      }
+    }
+    Dual<T, C> r = Energy<MAT, NDIM, Dual<T, C>>::psi(x, L.lam, L.mu);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      P[k] = r.d[k].v;
+      KdE[k] = r.d[k].d[0];
+    }
+    return r.v.v;
   }
-  return r.v.v;
+}
+
+// J2 history of the converged state at e: packed plastic strain and cumulative plastic strain
+template <int NDIM>
+__device__ inline void j2_commit(const double* e, const Local& L, double* hist_out) {
+  constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  double sig6[6], N6[6], dp;
+  bool pl;
+  j2_return<NDIM, double>(e, L, sig6, dp, N6, pl);
+  double n[C];
+  j2_pack<NDIM, double>(N6, n);
+#pragma unroll
+  for (int k = 0; k < C; ++k) hist_out[k] = L.hist[k] + dp * n[k];
+  hist_out[C] = L.hist[C] + dp;
 }
 
 // Determinant of the packed deformation gradient (finite strain domain check).

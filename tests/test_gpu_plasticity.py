@@ -1,0 +1,149 @@
+"""J2 plasticity on the HIP path against the CPU oracle (oracle/plasticity.py).
+
+The kernels return-map the stress from the voxel's plastic history with dual
+numbers, so K : d_eps is the forward-mode derivative of the return mapping; the
+oracle uses the closed-form consistent tangent.  Load paths with several
+increments and a second, unloading solve check that the history is committed
+between load steps exactly as the oracle does it.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import pack, rel
+from oracle import newton_cg
+from oracle import plasticity as OP
+from paper_2408_03804_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_FIELD = 1e-10
+TOL_HOMOG = 1e-11
+
+
+def make(shape, nphase=2, **kw):
+    from paper_2408_03804_amd.binding import FFTHomog
+    return FFTHomog(shape, "small", "j2_plastic", nphase, **kw)
+
+
+def table_j2(E=(1.0, 1.0), sy=(0.005, 0.01), H=(0.1, 0.2)):
+    return np.array([[*workloads.lame(E[i], 0.3), sy[i], H[i]] for i in range(2)])
+
+
+def fields(table, phase):
+    t = np.asarray(table)
+    return [t[phase, k] for k in range(4)]
+
+
+def to_full(field, shape):
+    d = len(shape)
+    a = field.cpu().numpy().reshape((d, d) + tuple(shape))
+    return np.moveaxis(a, (0, 1), (-2, -1))
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 4, 5)])
+def test_return_mapping_and_its_derivative_match_oracle(shape):
+    d = len(shape)
+    rng = np.random.default_rng(1)
+    phase = workloads.random_phases(shape, 2, 2)
+    tab = table_j2()
+    h = make(shape)
+    h.set_material(phase, tab)
+    A = 0.02 * rng.standard_normal(tuple(shape) + (d, d))
+    E = 0.5 * (A + np.swapaxes(A, -1, -2))
+    B = rng.standard_normal(tuple(shape) + (d, d))
+    dE = 0.5 * (B + np.swapaxes(B, -1, -2))
+    Pg, Kg, psig = h.debug_constitutive(pack(E, True), pack(dE, True))
+    lam, mu, sy, H = fields(tab, phase)
+    z = np.zeros(tuple(shape) + (3, 3))
+    zp = np.zeros(shape)
+    sig, dp, N = OP.return_map(E, z, zp, lam, mu, sy, H)
+    assert (dp > 0).mean() > 0.5
+    assert rel(Pg.cpu().numpy(), pack(sig[..., :d, :d], True)) < 1e-13
+    K = OP.tangent_apply(E, dE, z, zp, lam, mu, sy, H)
+    assert rel(Kg.cpu().numpy(), pack(K[..., :d, :d], True)) < 1e-12
+    ee = OP.embed(E) - dp[..., None, None] * N
+    psi = 0.5 * lam * np.einsum("...ii->...", ee) ** 2 + mu * np.einsum("...ij,...ij->...", ee, ee)
+    assert rel(psig.cpu().numpy(), psi) < 1e-12
+
+
+def run_path(shape, phase, tab, path, k_mode=0, tol_cg=1e-12):
+    """Run the same sequence of solves (macro, increments) on both sides; yield per-call comparisons."""
+    d = len(shape)
+    h = make(shape, tangent=True, tol_cg=tol_cg, k_mode=k_mode)
+    h.set_material(phase, tab)
+    lam, mu, sy, H = fields(tab, phase)
+    prob = OP.PlasticProblem(shape, lam, mu, sy, H)
+    state = None
+    out = []
+    for macro, n_inc in path:
+        S, psi, st = h.solve(macro, n_inc)
+        ref = newton_cg.solve(prob, macro, n_increments=n_inc, tol_cg=tol_cg, state=state)
+        state = ref["state"]
+        assert st["status"] == "ok" and ref["stats"]["status"] == "ok"
+        F = to_full(h.get_field(0), shape)
+        Pf = to_full(h.get_field(1), shape)
+        pl = h.get_field(3).cpu().numpy()
+        Fr = state.field
+        C, _ = h.tangent()
+        Cref, _ = OP.homogenized_tangent(prob, state, tol_cg=tol_cg)
+        out.append(dict(C=C, Cref=Cref,
+            S=S, Sref=ref["macro_stress"], psi=psi, psiref=ref["energy"], st=st, stref=ref["stats"],
+            field=rel(F - state.macro, Fr - state.macro), stress=rel(Pf, prob.stress(Fr)),
+            plastic=np.abs(pl - prob.plastic_strain_now(Fr)).max() / max(1e-30, np.abs(prob.plastic_strain_now(Fr)).max()),
+            pmax=float(pl.max())))
+    return h, prob, state, out
+
+
+def check(o):
+    assert np.abs(o["S"] - o["Sref"]).max() < TOL_HOMOG * np.abs(o["Sref"]).max()
+    assert abs(o["psi"] - o["psiref"]) < TOL_HOMOG * abs(o["psiref"])
+    assert o["field"] < TOL_FIELD and o["stress"] < TOL_FIELD
+    assert o["plastic"] < TOL_FIELD
+    assert abs(o["st"]["newton"] - o["stref"]["newton"]) <= 1
+    # homogenized consistent tangent of the step just solved
+    assert np.abs(o["C"] - o["Cref"]).max() < TOL_HOMOG * np.abs(o["Cref"]).max()
+
+
+def test_plane_strain_disk_biaxial_loading_then_unloading():
+    """Hard disk (twice the yield stress and hardening) in a soft matrix, biaxial eps = 1e-2 in
+    4 increments, then unloading to half in 2: fields, plastic strain and homogenized stress
+    against the oracle; the homogenized consistent tangent of the last step as well."""
+    n = 24
+    phase = workloads.centered_disk(n, 0.25)
+    tab = table_j2(E=(1.0, 2.0))
+    h, prob, state, out = run_path((n, n), phase, tab, [(np.array([1e-2, 1e-2, 0.0]), 4),
+                                                         (np.array([5e-3, 5e-3, 0.0]), 2),
+                                                         (np.array([1e-2, 1.5e-2, 4e-3]), 3)])
+    for o in out:
+        check(o)
+    assert out[0]["pmax"] > 1e-3
+    # the plastic tangent after loading is softer than the elastic one after unloading
+    assert out[0]["C"][0, 0] < 0.9 * out[1]["C"][0, 0]
+
+
+@pytest.mark.parametrize("k_mode", [0, 1])
+def test_three_dimensional_shear_path_both_tangent_modes(k_mode):
+    shape = (8, 7, 6)
+    phase = workloads.random_phases(shape, 2, 3)
+    tab = table_j2(E=(1.0, 2.0))
+    h, prob, state, out = run_path(shape, phase, tab, [(np.array([0, 0, 0, 0, 0, 2e-2]), 3),
+                                                       (np.array([5e-3, 0, 0, 0, 0, 1e-2]), 2)], k_mode=k_mode)
+    for o in out:
+        check(o)
+    assert out[0]["pmax"] > 0
+
+
+def test_set_field_restarts_with_a_virgin_history_and_j2_has_no_density_gradient():
+    from paper_2408_03804_amd.binding import FFTHomogError
+    shape = (10, 12)
+    phase = np.pad(workloads.centered_disk(10, 0.3), ((0, 0), (0, 2)))
+    h = make(shape)
+    h.set_material(phase, table_j2())
+    h.solve(np.array([1e-2, 0.0, 0.0]), 2)
+    assert h.get_field(3).cpu().numpy().max() > 0
+    h.reset()
+    assert h.get_field(3).cpu().numpy().max() == 0.0
+    with pytest.raises(FFTHomogError) as ei:
+        h.adjoint(np.zeros(3), 1.0)
+    assert ei.value.status == "eunsupported"

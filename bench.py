@@ -312,6 +312,73 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper_example(args, w, k_mode, paper_seconds, paper_note):
+    """One of the paper's 2D examples solved end to end: seconds per solve and voxel-iterations/s,
+    beside a bounded sample of the CPU oracle on the same cell."""
+    import torch
+
+    from paper_2408_03804_amd.binding import FFTHomog
+
+    shape = w["shape"]
+    N = int(np.prod(shape))
+    d = len(shape)
+    h = FFTHomog(shape, w["kinematics"], w["material"], 2, device="cuda:0", tol_newton=w["tol_newton"],
+                 tol_cg=w["tol_cg"], max_newton=50, max_cg=20000, k_mode=k_mode)
+    h.set_material(w["phase"], w["table"])
+
+    def step():
+        h.reset()
+        S, psi, st = h.solve(w["macro"], w["n_increments"])
+        if st["status"] != "ok":
+            raise RuntimeError("solve failed: %s" % st["status"])
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cg = 0
+    for _ in range(args.steps):
+        st = step()
+        cg += st["cg_total"]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import newton_cg, plasticity
+
+        tab = np.asarray(w["table"])
+        if w["material"] == "j2_plastic":
+            prob = plasticity.PlasticProblem(shape, tab[w["phase"], 0], tab[w["phase"], 1], tab[w["phase"], 2],
+                                             tab[w["phase"], 3])
+        else:
+            prob = newton_cg.Problem(shape, w["material"], tab[w["phase"], 0], tab[w["phase"], 1])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ref = newton_cg.solve(prob, w["macro"], n_increments=w["n_increments"], tol_newton=w["tol_newton"],
+                                  tol_cg=w["tol_cg"])
+            tc = time.perf_counter() - t0
+        cpu = {"value": 1.0 / tc, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "the full solve of the same cell by the CPU oracle, single thread, %.1f s "
+                         "(%d Newton, %d CG iterations)" % (tc, ref["stats"]["newton"], ref["stats"]["cg_total"])}
+    out = {
+        "metric": "seconds per solve, %s" % w["name"],
+        "value": wall, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w["name"], "grid": list(shape), "material": w["material"],
+                   "n_increments": w["n_increments"], "k_mode": "stored" if k_mode else "recompute",
+                   "newton_iterations": st["newton"], "cg_iterations": st["cg_total"],
+                   "voxel_iters_per_s": N * cg / (wall * args.steps),
+                   "paper_seconds_context": paper_seconds, "paper_context": paper_note},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,7 +397,8 @@ def main():
     ap.add_argument("--check-tol", type=float, default=0.02)
     ap.add_argument("--max-spread", type=float, default=0.03)
     ap.add_argument("--members", type=int, default=2)
-    ap.add_argument("--workload", default="nh128", choices=["nh128", "uq256", "tangents32", "surrogate32"],
+    ap.add_argument("--workload", default="nh128",
+                    choices=["nh128", "uq256", "tangents32", "surrogate32", "e2_stvk299", "e3_j2_199"],
                     help="nh128: the Newton-CG solve (default); uq256: tangents of 256 cells of uneven size; "
                          "tangents32: tangents of 1024 cells of 32^3")
     ap.add_argument("--no-graph", action="store_true")
@@ -370,6 +438,12 @@ def main():
         return
     if args.workload == "surrogate32":
         return bench_surrogate(args)
+    if args.workload == "e2_stvk299":
+        return bench_paper_example(args, workloads.workload_e2_stvk(), 0, 19.5,
+                                   "JAX on one CPU core of an EPYC 9654, AD via jvp (the paper's section 4.1.1)")
+    if args.workload == "e3_j2_199":
+        return bench_paper_example(args, workloads.workload_e3_j2(), 1, 0.25,
+                                   "JAX on one CPU core of an EPYC 9654, AD via linearize (the paper's section 4.1.2)")
     if args.workload == "uq256":
         cells = workloads.workload_uq_cells(256)
         log("workload generated")

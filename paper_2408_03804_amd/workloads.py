@@ -248,3 +248,36 @@ def workload_tangent_cells(n_cells=1024, n=32, seed=0, correlation_length=8.0, s
                               table=np.array([lame(E[i, 0], 0.3), lame(E[i, 1], 0.3)]), seed=i,
                               correlation_length=correlation_length, stiff_fraction=stiff_fraction))
     return cells
+
+
+def corner_square(n, fraction):
+    """2D square inclusion of edge fraction * n at the (0, 0) corner: voxel centres inside [0, f L)^2."""
+    x = np.arange(n) + 0.5
+    inside = x < fraction * n
+    return (inside[:, None] & inside[None, :]).astype(np.uint8)
+
+
+def workload_e2_stvk(n=299, contrast=10.0):
+    """The paper's hyperelastic example: 2D St. Venant-Kirchhoff cell with a stiff square inclusion of
+    edge L/3 at a corner, simple shear F-bar = [[1, 0.1], [0, 1]] in one increment, Newton tolerance
+    1e-5, CG tolerance 1e-8.  The stiffness contrast is not stated; 10 (both Lame parameters) is the
+    reading used, with matrix E = 1, nu = 0.3."""
+    lm0 = lame(1.0, 0.3)
+    lm1 = lame(contrast, 0.3)
+    F = np.eye(2)
+    F[0, 1] = 0.1
+    return dict(name="e2_stvk_%d" % n, ndim=2, shape=(n, n), kinematics="finite", material="stvk",
+                phase=corner_square(n, 1.0 / 3.0), table=np.array([lm0, lm1]), macro=F.reshape(-1),
+                n_increments=1, tol_newton=1e-5, tol_cg=1e-8)
+
+
+def workload_e3_j2(n=199, n_increments=10):
+    """The paper's elastoplastic example: 2D plane-strain J2 cell with a hard circular inclusion (twice
+    the matrix yield stress and hardening modulus), biaxial macro strain [1e-2, 1e-2, 0].  Not stated,
+    and read here: inclusion radius L/4, E = 1, nu = 0.3 in both phases, matrix sig_y = 5e-3,
+    H = 0.1, and the load applied in 10 increments."""
+    lm = lame(1.0, 0.3)
+    table = np.array([[lm[0], lm[1], 5e-3, 0.1], [lm[0], lm[1], 1e-2, 0.2]])
+    return dict(name="e3_j2_%d" % n, ndim=2, shape=(n, n), kinematics="small", material="j2_plastic",
+                phase=centered_disk(n, 0.25), table=table, macro=np.array([1e-2, 1e-2, 0.0]),
+                n_increments=n_increments, tol_newton=1e-10, tol_cg=1e-10)

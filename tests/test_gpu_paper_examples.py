@@ -1,0 +1,67 @@
+"""The paper's two constitutive examples at their own grid sizes, against the CPU oracle.
+
+E2 (section 4.1.1): 2D St. Venant-Kirchhoff, 299^2 (= 13 * 23 points per axis, so the FFT runs
+its generic prime stages), one increment, Newton tolerance 1e-5, CG tolerance 1e-8.  The paper
+reports identical residual norms and iteration counts for AD and analytic tangents; here the GPU
+(dual numbers) and the oracle (closed form) must take the same Newton and CG iteration counts,
+and the fields agree to the CG tolerance.
+E3 (section 4.1.2): 2D plane-strain J2 plasticity, 199^2, biaxial load in 10 increments, with
+the stored (linearised) tangent in CG as in the paper.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import rel
+from oracle import newton_cg, plasticity
+from paper_2408_03804_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def to_full(field, shape):
+    d = len(shape)
+    a = field.cpu().numpy().reshape((d, d) + tuple(shape))
+    return np.moveaxis(a, (0, 1), (-2, -1))
+
+
+def run(w, prob, k_mode):
+    from paper_2408_03804_amd.binding import FFTHomog
+    shape = w["shape"]
+    h = FFTHomog(shape, w["kinematics"], w["material"], 2, tol_newton=w["tol_newton"], tol_cg=w["tol_cg"],
+                 max_cg=20000, k_mode=k_mode)
+    h.set_material(w["phase"], w["table"])
+    S, psi, st = h.solve(w["macro"], w["n_increments"])
+    ref = newton_cg.solve(prob, w["macro"], n_increments=w["n_increments"], tol_newton=w["tol_newton"],
+                          tol_cg=w["tol_cg"])
+    assert st["status"] == "ok" and ref["stats"]["status"] == "ok"
+    F = to_full(h.get_field(0), shape)
+    Fr = ref["state"].field
+    return h, S, st, ref, F, Fr
+
+
+def test_e2_stvk_299_same_iterations_as_the_analytic_tangent():
+    w = workloads.workload_e2_stvk()
+    tab = w["table"]
+    prob = newton_cg.Problem(w["shape"], "stvk", tab[w["phase"], 0], tab[w["phase"], 1])
+    h, S, st, ref, F, Fr = run(w, prob, 0)
+    assert st["newton"] == ref["stats"]["newton"]
+    assert st["cg"] == ref["stats"]["cg"]
+    Fbar = ref["state"].macro
+    assert rel(F - Fbar, Fr - Fbar) < 1e-6
+    assert np.abs(S - ref["macro_stress"]).max() < 1e-7 * np.abs(ref["macro_stress"]).max()
+
+
+def test_e3_j2_199_stored_tangent():
+    w = workloads.workload_e3_j2()
+    tab = w["table"]
+    ph = w["phase"]
+    prob = plasticity.PlasticProblem(w["shape"], tab[ph, 0], tab[ph, 1], tab[ph, 2], tab[ph, 3])
+    h, S, st, ref, F, Fr = run(w, prob, 1)
+    assert abs(st["newton"] - ref["stats"]["newton"]) <= 1
+    Fbar = ref["state"].macro
+    assert rel(F - Fbar, Fr - Fbar) < 1e-10
+    assert np.abs(S - ref["macro_stress"]).max() < 1e-11 * np.abs(ref["macro_stress"]).max()
+    p = h.get_field(3).cpu().numpy()
+    pr = prob.plastic_strain_now(Fr)
+    assert pr.max() > 0 and np.abs(p - pr).max() < 1e-10 * pr.max()

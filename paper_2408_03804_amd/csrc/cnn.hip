@@ -27,6 +27,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kT = 256;
 constexpr int BM = 64, BN = 64, BK = 32, LDT = BK + 8;  // GEMM tile; LDS row pitch in bf16
 constexpr int kMaxSplits = 1024;
+constexpr int kColRows = 256;  // rows per block of the bias-gradient column sums
 
 // fp32 -> bf16, round to nearest even (NaN stays NaN)
 __host__ __device__ inline bf16 to_bf16(float f) {
@@ -186,50 +187,84 @@ int splits_for(int K, int rows) { return std::max(1, std::min(kMaxSplits, (K + r
 // ---------------------------------------------------------------------------
 inline unsigned blocks(long long n) { return (unsigned)std::min<long long>((n + kT - 1) / kT, 1 << 20); }
 
-// col[(b,o)][k] for k = t * Ci + ci < 27 Ci (zero beyond): the input voxel of tap t of output o
-// in a periodic stride-2 window; src is bf16 channels-last or (layer 1) the u8 phase map.
-__global__ void k_im2col(const bf16* src, const uint8_t* phase, int B, int n, int Ci, int Kp, bf16* col, int* bad) {
+// im2col of a periodic stride-2 3x3x3 window: col[(b,o)][t * Ci + ci] = a[b, (2 o + t - 1) mod n, ci]
+// (zero for k >= 27 Ci).  One thread per (output row, tap) copies the tap's Ci channels, 16 bytes
+// at a time when Ci is a multiple of 8 (rows of src and col are then 16-byte aligned).
+__global__ void k_im2col(const bf16* src, int B, int n, int Ci, int Kp, bf16* col) {
   const int m = n / 2;
   const long long rows = (long long)B * m * m * m;
-  const long long tot = rows * Kp;
+  const long long tot = rows * 27;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
-    const long long row = e / Kp;
-    const int k = (int)(e - row * Kp);
-    bf16 v = 0;
-    if (k < 27 * Ci) {
-      const int t = k / Ci;
-      const int ci = k - t * Ci;
-      const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
-      long long r = row;
-      const int ox = (int)(r % m);
-      r /= m;
-      const int oy = (int)(r % m);
-      r /= m;
-      const int oz = (int)(r % m);
-      const long long b = r / m;
-      const int iz = (2 * oz + tz - 1 + n) % n, iy = (2 * oy + ty - 1 + n) % n, ix = (2 * ox + tx - 1 + n) % n;
-      const long long vox = ((b * n + iz) * n + iy) * n + ix;
-      if (phase) {
-        const uint8_t p = phase[vox];
-        if (p > 1) *bad = 1;
-        v = p ? (bf16)0x3f80 : (bf16)0;
-      } else {
-        v = src[vox * Ci + ci];
-      }
+    const long long row = e / 27;
+    const int t = (int)(e - row * 27);
+    const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+    long long r = row;
+    const int ox = (int)(r % m);
+    r /= m;
+    const int oy = (int)(r % m);
+    r /= m;
+    const int oz = (int)(r % m);
+    const long long b = r / m;
+    const int iz = (2 * oz + tz - 1 + n) % n, iy = (2 * oy + ty - 1 + n) % n, ix = (2 * ox + tx - 1 + n) % n;
+    const bf16* sp = src + (((b * n + iz) * n + iy) * n + ix) * Ci;
+    bf16* dp = col + row * Kp + (long long)t * Ci;
+    if ((Ci & 7) == 0) {
+      for (int c = 0; c < Ci; c += 8) *reinterpret_cast<uint4*>(dp + c) = *reinterpret_cast<const uint4*>(sp + c);
+    } else {
+      for (int c = 0; c < Ci; ++c) dp[c] = sp[c];
     }
-    col[e] = v;
+    if (t == 26)
+      for (int k = 27 * Ci; k < Kp; ++k) col[row * Kp + k] = 0;
   }
 }
 
-// pre[m][n] += bias[n]; act[m][n] = bf16(gelu(pre))   (act may be null)
-__global__ void k_bias_gelu(float* pre, const float* bias, long long M, int N, bf16* act) {
-  const long long tot = M * N;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(e % N);
-    const float x = pre[e] + bias[c];
-    pre[e] = x;
-    if (act) act[e] = to_bf16(gelu(x));
+// First block: the input is the u8 phase map (one channel); one thread per output row writes
+// its Kp entries (27 taps, then zeros).  Ids above 1 raise *bad.
+__global__ void k_im2col_phase(const uint8_t* phase, int B, int n, int Kp, bf16* col, int* bad) {
+  const int m = n / 2;
+  const long long rows = (long long)B * m * m * m;
+  for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < rows;
+       row += (long long)gridDim.x * blockDim.x) {
+    long long r = row;
+    const int ox = (int)(r % m);
+    r /= m;
+    const int oy = (int)(r % m);
+    r /= m;
+    const int oz = (int)(r % m);
+    const long long b = r / m;
+    const uint8_t* pb = phase + b * n * n * n;
+    bf16* dp = col + row * Kp;
+    int t = 0;
+    for (int tz = 0; tz < 3; ++tz) {
+      const int iz = (2 * oz + tz - 1 + n) % n;
+      for (int ty = 0; ty < 3; ++ty) {
+        const int iy = (2 * oy + ty - 1 + n) % n;
+        for (int tx = 0; tx < 3; ++tx, ++t) {
+          const int ix = (2 * ox + tx - 1 + n) % n;
+          const uint8_t p = pb[((long long)iz * n + iy) * n + ix];
+          if (p > 1) *bad = 1;
+          dp[t] = p ? (bf16)0x3f80 : (bf16)0;
+        }
+      }
+    }
+    for (int k = 27; k < Kp; ++k) dp[k] = 0;
   }
+}
+
+// pre[m][n] += bias[n]; act[m][n] = bf16(gelu(pre))   (act may be null).  A block covers
+// kT / N rows (N <= kT) or one row in chunks (N > kT); no per-element division.
+__global__ void k_bias_gelu(float* pre, const float* bias, long long M, int N, bf16* act) {
+  const int rpb = N <= kT ? kT / N : 1;
+  const int c0 = N <= kT ? (int)threadIdx.x % N : (int)threadIdx.x;
+  const int rr = N <= kT ? (int)threadIdx.x / N : 0;
+  if (rr >= rpb) return;
+  for (long long r = (long long)blockIdx.x * rpb + rr; r < M; r += (long long)gridDim.x * rpb)
+    for (int c = c0; c < N; c += (N <= kT ? N : kT)) {
+      const long long e = r * N + c;
+      const float x = pre[e] + bias[c];
+      pre[e] = x;
+      if (act) act[e] = to_bf16(gelu(x));
+    }
 }
 
 // x5[b][:] = [bf16(mean over V voxels of gelu(pre4[b])), bf16(feat[b]), 0 ...]
@@ -307,6 +342,22 @@ __global__ void k_colsum_partial(const float* X, long long M, int C, long long r
   }
 }
 
+// dst[c] = sum over blocks of partial[blk][c]: one block per column, thread-strided partial sums
+// combined by a fixed tree
+__global__ void k_colsum_final(const float* partial, int nb, int C, float* dst) {
+  __shared__ float red[kT];
+  const int c = blockIdx.x;
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < nb; i += kT) acc += partial[(long long)i * C + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dst[c] = red[0];
+}
+
 // out[n] = sum_s P[s][n] in order (n < N); with `rows`>1, P is [S][rows][N] and out [rows][ldo]
 __global__ void k_sum_splits(const float* P, int S, long long rows, int N, int Nvalid, float* out, int ldo, int accumulate) {
   const long long tot = rows * Nvalid;
@@ -349,14 +400,14 @@ __global__ void k_unpool_back(const float* dx5, int ldx, const float* pre4, int 
 // Gather of dcol back to the input voxels of a stride-2 periodic layer, times gelu'(pre_in):
 // voxel i of an axis of length n is tap t of output o when 2 o + t - 1 = i (mod n), i.e. t = 1
 // (o = i/2) for even i and t = 0 (o = (i+1)/2 mod n/2) or t = 2 (o = (i-1)/2) for odd i.
+// One thread per input voxel finds its (up to 8) (output row, tap) pairs once and sums them for
+// every channel, four channels at a time when Ci is a multiple of 4.
 __global__ void k_col2im_gelu(const float* dcol, int B, int n, int Ci, int Kp, const float* pre_in, float* d32,
                               bf16* db) {
   const int m = n / 2;
-  const long long tot = (long long)B * n * n * n * Ci;
+  const long long tot = (long long)B * n * n * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
     long long r = e;
-    const int ci = (int)(r % Ci);
-    r /= Ci;
     const int ix = (int)(r % n);
     r /= n;
     const int iy = (int)(r % n);
@@ -381,17 +432,44 @@ __global__ void k_col2im_gelu(const float* dcol, int B, int n, int Ci, int Kp, c
     taps(iz, tz, oz, nzc);
     taps(iy, ty, oy, nyc);
     taps(ix, tx, ox, nxc);
-    float s = 0.f;
+    long long src[8];
+    int np = 0;
     for (int a = 0; a < nzc; ++a)
       for (int c = 0; c < nyc; ++c)
         for (int d = 0; d < nxc; ++d) {
           const long long orow = ((b * m + oz[a]) * m + oy[c]) * m + ox[d];
           const int t = (tz[a] * 3 + ty[c]) * 3 + tx[d];
-          s += dcol[orow * Kp + t * Ci + ci];
+          src[np++] = orow * Kp + (long long)t * Ci;
         }
-    const float v = s * gelu_grad(pre_in[e]);
-    d32[e] = v;
-    db[e] = to_bf16(v);
+    const long long base = e * Ci;
+    if ((Ci & 3) == 0) {
+      for (int ci = 0; ci < Ci; ci += 4) {
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = 0; q < np; ++q) {
+          const float4 v = *reinterpret_cast<const float4*>(dcol + src[q] + ci);
+          s.x += v.x;
+          s.y += v.y;
+          s.z += v.z;
+          s.w += v.w;
+        }
+        const float4 pr = *reinterpret_cast<const float4*>(pre_in + base + ci);
+        const float o0 = s.x * gelu_grad(pr.x), o1 = s.y * gelu_grad(pr.y), o2 = s.z * gelu_grad(pr.z),
+                    o3 = s.w * gelu_grad(pr.w);
+        *reinterpret_cast<float4*>(d32 + base + ci) = make_float4(o0, o1, o2, o3);
+        db[base + ci] = to_bf16(o0);
+        db[base + ci + 1] = to_bf16(o1);
+        db[base + ci + 2] = to_bf16(o2);
+        db[base + ci + 3] = to_bf16(o3);
+      }
+    } else {
+      for (int ci = 0; ci < Ci; ++ci) {
+        float s = 0.f;
+        for (int q = 0; q < np; ++q) s += dcol[src[q] + ci];
+        const float v = s * gelu_grad(pre_in[base + ci]);
+        d32[base + ci] = v;
+        db[base + ci] = to_bf16(v);
+      }
+    }
   }
 }
 
@@ -637,7 +715,7 @@ void plan(const fft_homog_cnn_desc* d, Plan* L) {
   L->scratch_floats = sc;
   L->o_scratch = take(sc * 4);
   const long long M1 = Bm * (long long)L->edge[1] * L->edge[1] * L->edge[1];
-  L->colpart_floats = (size_t)((M1 + 4095) / 4096 + 1) * std::max(std::max(1024, d->n_out), d->hidden);
+  L->colpart_floats = (size_t)((M1 + kColRows - 1) / kColRows + 1) * std::max(std::max(1024, d->n_out), d->hidden);
   L->o_colpart = take(L->colpart_floats * 4);
   L->o_loss = take(64);
   L->o_flag = take(64);
@@ -650,12 +728,12 @@ void plan(const fft_homog_cnn_desc* d, Plan* L) {
     if (e_ != hipSuccess) return FFT_HOMOG_EDEVICE;     \
   } while (0)
 
-// bias gradient: column sums of X [M][C] into dst[C]
+// bias gradient: column sums of X [M][C] into dst[C], two fixed-order stages
 hipError_t colsum(fft_homog_cnn_t* h, const float* X, long long M, int C, float* dst) {
-  const long long rpb = 4096;
+  const long long rpb = kColRows;
   const long long nb = (M + rpb - 1) / rpb;
   hipLaunchKernelGGL(k_colsum_partial, dim3((unsigned)nb), dim3(kT), 0, h->s, X, M, C, rpb, h->colpart);
-  hipLaunchKernelGGL(k_sum_splits, dim3(blocks(C)), dim3(kT), 0, h->s, h->colpart, (int)nb, 1LL, C, C, dst, C, 0);
+  hipLaunchKernelGGL(k_colsum_final, dim3(C), dim3(kT), 0, h->s, h->colpart, (int)nb, C, dst);
   return hipGetLastError();
 }
 
@@ -668,8 +746,11 @@ int forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat, int B) 
   for (int l = 1; l <= 4; ++l) {
     const int n = h->edge[l - 1];
     const long long Ml = (long long)B * h->edge[l] * h->edge[l] * h->edge[l];
-    hipLaunchKernelGGL(k_im2col, dim3(blocks(Ml * h->Kp[l])), dim3(kT), 0, h->s, l == 1 ? nullptr : h->act[l - 1],
-                       l == 1 ? phase : nullptr, B, n, ch[l - 1], h->Kp[l], h->col[l], h->flag);
+    if (l == 1)
+      hipLaunchKernelGGL(k_im2col_phase, dim3(blocks(Ml)), dim3(kT), 0, h->s, phase, B, n, h->Kp[1], h->col[1], h->flag);
+    else
+      hipLaunchKernelGGL(k_im2col, dim3(blocks(Ml * 27)), dim3(kT), 0, h->s, h->act[l - 1], B, n, ch[l - 1], h->Kp[l],
+                         h->col[l]);
     CK(hipGetLastError());
     CK(gemm((int)Ml, ch[l], h->Kp[l], h->col[l], h->Kp[l], 1, h->Wb[l], h->Kp[l], 1, h->pre[l], 1, h->s));
     hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(Ml * ch[l])), dim3(kT), 0, h->s, h->pre[l], h->p + h->offB[l], Ml, ch[l],
@@ -891,7 +972,7 @@ int fft_homog_cnn_loss_grad(fft_homog_cnn_t* h, const uint8_t* phase, const floa
       CK(gemm((int)Ml, h->Kp[l], ch[l], db, ch[l], 1, h->Wb[l], 1, h->Kp[l], h->dcol, 1, h->s));
       const int nin = h->edge[l - 1];
       const long long Min = (long long)B * nin * nin * nin;
-      hipLaunchKernelGGL(k_col2im_gelu, dim3(blocks(Min * ch[l - 1])), dim3(kT), 0, h->s, h->dcol, B, nin, ch[l - 1],
+      hipLaunchKernelGGL(k_col2im_gelu, dim3(blocks(Min)), dim3(kT), 0, h->s, h->dcol, B, nin, ch[l - 1],
                          h->Kp[l], h->pre[l - 1], n32, nb);
       CK(hipGetLastError());
       std::swap(d32, n32);

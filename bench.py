@@ -404,6 +404,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="many-cell workloads: keep the default launch shape")
     ap.add_argument("--autotune", action="store_true", help="nh128: tune the launch shape before timing")
+    ap.add_argument("--graph", action="store_true", help="nh128: replay CG chunks from a captured HIP graph")
     ap.add_argument("--max-gb", type=float, default=96.0, help="workspace budget per multi-cell handle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -464,7 +465,7 @@ def main():
     c = 9
     log("workload %s generated" % w["name"])
     h = FFTHomog(shape, "finite", "neo_hookean", 2, device="cuda:0", tol_newton=1e-10, tol_cg=1e-10,
-                 max_newton=50, max_cg=20000, k_mode=args.k_mode)
+                 max_newton=50, max_cg=20000, k_mode=args.k_mode, graph=args.graph)
     h.set_material(w["phase"], w["table"])
     shape_info = h.launch_shape()
     if args.autotune:
@@ -541,7 +542,7 @@ def main():
                    "random field (l=8 voxels) thresholded at 30%% stiff, mu 1 vs 20, lam=2mu, F-bar=diag(1.05,1,1) "
                    "in 10 increments, Newton/CG tol 1e-10, tangent by dual-number JVP" % n,
                    "grid": [n, n, n], "n_increments": w["n_increments"], "k_mode": "stored" if args.k_mode else "recompute",
-                   "launch_shape": shape_info,
+                   "launch_shape": shape_info, "graph": args.graph,
                    "cg_iterations_per_step": [s["cg_total"] for s in stats],
                    "newton_iterations_per_step": [s["newton"] for s in stats]},
         "roofline": roofline,

@@ -234,6 +234,8 @@ __global__ void k_im2col_phase(const uint8_t* phase, int B, int n, int Kp, bf16*
     const long long b = r / m;
     const uint8_t* pb = phase + b * n * n * n;
     bf16* dp = col + row * Kp;
+    // the 27 taps as bits, then 16-byte stores of the bf16 row (Kp is a multiple of 32)
+    uint32_t bits = 0;
     int t = 0;
     for (int tz = 0; tz < 3; ++tz) {
       const int iz = (2 * oz + tz - 1 + n) % n;
@@ -243,11 +245,20 @@ __global__ void k_im2col_phase(const uint8_t* phase, int B, int n, int Kp, bf16*
           const int ix = (2 * ox + tx - 1 + n) % n;
           const uint8_t p = pb[((long long)iz * n + iy) * n + ix];
           if (p > 1) *bad = 1;
-          dp[t] = p ? (bf16)0x3f80 : (bf16)0;
+          bits |= (p ? 1u : 0u) << t;
         }
       }
     }
-    for (int k = 27; k < Kp; ++k) dp[k] = 0;
+    for (int k0 = 0; k0 < Kp; k0 += 8) {
+      uint32_t wv[4];
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 2 * q;
+        const uint32_t lo = (k < 27 && ((bits >> k) & 1u)) ? 0x3f80u : 0u;
+        const uint32_t hi = (k + 1 < 27 && ((bits >> (k + 1)) & 1u)) ? 0x3f80u : 0u;
+        wv[q] = lo | (hi << 16);
+      }
+      *reinterpret_cast<uint4*>(dp + k0) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    }
   }
 }
 
@@ -400,14 +411,18 @@ __global__ void k_unpool_back(const float* dx5, int ldx, const float* pre4, int 
 // Gather of dcol back to the input voxels of a stride-2 periodic layer, times gelu'(pre_in):
 // voxel i of an axis of length n is tap t of output o when 2 o + t - 1 = i (mod n), i.e. t = 1
 // (o = i/2) for even i and t = 0 (o = (i+1)/2 mod n/2) or t = 2 (o = (i-1)/2) for odd i.
-// One thread per input voxel finds its (up to 8) (output row, tap) pairs once and sums them for
-// every channel, four channels at a time when Ci is a multiple of 4.
+// One thread per (input voxel, group of 4 channels; 1 channel when Ci is not a multiple of 4):
+// consecutive threads read consecutive channels of the same dcol rows.
 __global__ void k_col2im_gelu(const float* dcol, int B, int n, int Ci, int Kp, const float* pre_in, float* d32,
                               bf16* db) {
   const int m = n / 2;
-  const long long tot = (long long)B * n * n * n;
+  const int w = (Ci & 3) == 0 ? 4 : 1;
+  const int groups = Ci / w;
+  const long long tot = (long long)B * n * n * n * groups;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
-    long long r = e;
+    const long long vox = e / groups;
+    const int ci = (int)(e - vox * groups) * w;
+    long long r = vox;
     const int ix = (int)(r % n);
     r /= n;
     const int iy = (int)(r % n);
@@ -432,43 +447,36 @@ __global__ void k_col2im_gelu(const float* dcol, int B, int n, int Ci, int Kp, c
     taps(iz, tz, oz, nzc);
     taps(iy, ty, oy, nyc);
     taps(ix, tx, ox, nxc);
-    long long src[8];
-    int np = 0;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int a = 0; a < nzc; ++a)
       for (int c = 0; c < nyc; ++c)
         for (int d = 0; d < nxc; ++d) {
           const long long orow = ((b * m + oz[a]) * m + oy[c]) * m + ox[d];
           const int t = (tz[a] * 3 + ty[c]) * 3 + tx[d];
-          src[np++] = orow * Kp + (long long)t * Ci;
+          const float* src = dcol + orow * Kp + (long long)t * Ci + ci;
+          if (w == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+          } else {
+            s.x += src[0];
+          }
         }
-    const long long base = e * Ci;
-    if ((Ci & 3) == 0) {
-      for (int ci = 0; ci < Ci; ci += 4) {
-        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int q = 0; q < np; ++q) {
-          const float4 v = *reinterpret_cast<const float4*>(dcol + src[q] + ci);
-          s.x += v.x;
-          s.y += v.y;
-          s.z += v.z;
-          s.w += v.w;
-        }
-        const float4 pr = *reinterpret_cast<const float4*>(pre_in + base + ci);
-        const float o0 = s.x * gelu_grad(pr.x), o1 = s.y * gelu_grad(pr.y), o2 = s.z * gelu_grad(pr.z),
-                    o3 = s.w * gelu_grad(pr.w);
-        *reinterpret_cast<float4*>(d32 + base + ci) = make_float4(o0, o1, o2, o3);
-        db[base + ci] = to_bf16(o0);
-        db[base + ci + 1] = to_bf16(o1);
-        db[base + ci + 2] = to_bf16(o2);
-        db[base + ci + 3] = to_bf16(o3);
-      }
+    const long long base = vox * Ci + ci;
+    if (w == 4) {
+      const float4 pr = *reinterpret_cast<const float4*>(pre_in + base);
+      const float o0 = s.x * gelu_grad(pr.x), o1 = s.y * gelu_grad(pr.y), o2 = s.z * gelu_grad(pr.z),
+                  o3 = s.w * gelu_grad(pr.w);
+      *reinterpret_cast<float4*>(d32 + base) = make_float4(o0, o1, o2, o3);
+      const uint2 packed = make_uint2((uint32_t)to_bf16(o0) | ((uint32_t)to_bf16(o1) << 16),
+                                      (uint32_t)to_bf16(o2) | ((uint32_t)to_bf16(o3) << 16));
+      *reinterpret_cast<uint2*>(db + base) = packed;
     } else {
-      for (int ci = 0; ci < Ci; ++ci) {
-        float s = 0.f;
-        for (int q = 0; q < np; ++q) s += dcol[src[q] + ci];
-        const float v = s * gelu_grad(pre_in[base + ci]);
-        d32[base + ci] = v;
-        db[base + ci] = to_bf16(v);
-      }
+      const float v = s.x * gelu_grad(pre_in[base]);
+      d32[base] = v;
+      db[base] = to_bf16(v);
     }
   }
 }
@@ -972,7 +980,7 @@ int fft_homog_cnn_loss_grad(fft_homog_cnn_t* h, const uint8_t* phase, const floa
       CK(gemm((int)Ml, h->Kp[l], ch[l], db, ch[l], 1, h->Wb[l], 1, h->Kp[l], h->dcol, 1, h->s));
       const int nin = h->edge[l - 1];
       const long long Min = (long long)B * nin * nin * nin;
-      hipLaunchKernelGGL(k_col2im_gelu, dim3(blocks(Min)), dim3(kT), 0, h->s, h->dcol, B, nin, ch[l - 1],
+      hipLaunchKernelGGL(k_col2im_gelu, dim3(blocks(Min * ch[l - 1])), dim3(kT), 0, h->s, h->dcol, B, nin, ch[l - 1],
                          h->Kp[l], h->pre[l - 1], n32, nb);
       CK(hipGetLastError());
       std::swap(d32, n32);

@@ -34,15 +34,17 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = ["xfwd_cgop", "reduce_pq", "y_fwd", "outer_project", "y_inv", "xinv_cgupdate", "reduce_rr"]
 
 
+CG_KERNEL_SOURCES = ["common.h", "dual.h", "fft_lds.h", "kernels.h", "kernels.hip", "materials.h"]
+
+
 def kernel_source_hash():
-    """sha256 of the HIP sources; HBM counter records are valid only for the sources they were taken on."""
-    import glob
+    """sha256 of the sources of the CG-iteration kernels (device code and the headers it includes);
+    HBM counter records are valid only for the kernels they were taken on."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2408_03804_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h")):
-            h.update(open(f, "rb").read())
+    for f in CG_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2408_03804_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 

@@ -78,6 +78,10 @@ enum { FFT_HOMOG_K_RECOMPUTE = 0, FFT_HOMOG_K_STORED = 1 };
 /* flags */
 #define FFT_HOMOG_FLAG_TANGENT 1u  /* size the workspace for the ncomp-RHS tangent solve */
 #define FFT_HOMOG_FLAG_DENSITY 2u  /* reserve a per-voxel density field (SIMP scaling) */
+#define FFT_HOMOG_FLAG_PLANE_STRESS 8u /* 2D linear elasticity under plane stress (sig_33 = 0) instead of
+                                          plane strain: the law becomes 2D linear elasticity with the
+                                          reduced first Lame parameter 2 lam mu / (lam + 2 mu); EINVAL
+                                          for 3D or other materials */
 #define FFT_HOMOG_FLAG_GRAPH 4u    /* enqueue full chunks of CG iterations by replaying a captured
                                       HIP graph (built on first use, rebuilt after set_material or
                                       autotune); results are bitwise those of direct launches */
@@ -87,7 +91,8 @@ enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_E
 
 typedef struct fft_homog_desc {
   int ndim;          /* 2 or 3 */
-  int n[3];          /* grid points along x, y, z; each 1..1024 with prime factors <= 61 */
+  int n[3];          /* grid points along x, y, z; each 1..1024 (prime factors above 16 use a direct
+                        DFT stage of that length: correct, but slower per point than radix stages) */
   double len[3];     /* cell edge lengths along x, y, z (> 0); wavevector xi = 2 pi k / len */
   int kinematics;    /* FFT_HOMOG_SMALL_STRAIN or FFT_HOMOG_FINITE_STRAIN */
   int material;      /* LINEAR_ELASTIC or J2_PLASTIC (small), NEO_HOOKEAN or STVK (finite); J2

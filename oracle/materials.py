@@ -75,6 +75,36 @@ class LinearElastic:
         return np.broadcast_to(base, eps.shape[:-2] + (d, d, d, d)).copy()
 
 
+class LinearElasticPlaneStress:
+    """2D linear elasticity under plane stress: the out-of-plane strain eps_33 takes the value that
+    makes sigma_33 of the 3D law vanish, eps_33 = -lam tr(eps) / (lam + 2 mu); stress, tangent and
+    energy are those of the 3D law at that strain (the in-plane block of the stress)."""
+
+    kinematics = "small"
+
+    @staticmethod
+    def _full(eps, lam, mu):
+        lam = np.asarray(lam, dtype=np.float64)
+        mu = np.asarray(mu, dtype=np.float64)
+        e3 = np.zeros(eps.shape[:-2] + (3, 3), dtype=eps.dtype)
+        e3[..., :2, :2] = eps
+        e3[..., 2, 2] = -lam * _tr(eps) / (lam + 2.0 * mu)
+        return e3
+
+    @staticmethod
+    def stress(eps, lam, mu):
+        e3 = LinearElasticPlaneStress._full(eps, lam, mu)
+        return LinearElastic.stress(e3, lam, mu)[..., :2, :2]
+
+    @staticmethod
+    def tangent_apply(eps, deps, lam, mu):
+        return LinearElasticPlaneStress.stress(deps, lam, mu)
+
+    @staticmethod
+    def psi(eps, lam, mu):
+        return LinearElastic.psi(LinearElasticPlaneStress._full(eps, lam, mu), lam, mu)
+
+
 # ----------------------------------------------------------------------------
 # finite strain, compressible Neo-Hookean
 # ----------------------------------------------------------------------------
@@ -179,6 +209,7 @@ class StVenantKirchhoff:
 
 MATERIALS = {
     "linear_elastic": LinearElastic,
+    "linear_elastic_plane_stress": LinearElasticPlaneStress,
     "neo_hookean": NeoHookean,
     "stvk": StVenantKirchhoff,
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfft_homog.so")
 SMALL_STRAIN, FINITE_STRAIN = 0, 1
 LINEAR_ELASTIC, NEO_HOOKEAN, STVK, J2_PLASTIC = 0, 1, 2, 3
 K_RECOMPUTE, K_STORED = 0, 1
-FLAG_TANGENT, FLAG_DENSITY, FLAG_GRAPH = 1, 2, 4
+FLAG_TANGENT, FLAG_DENSITY, FLAG_GRAPH, FLAG_PLANE_STRESS = 1, 2, 4, 8
 FIELD_STRAIN, FIELD_STRESS, FIELD_ENERGY, FIELD_PLASTIC = 0, 1, 2, 3
 MAX_RECORDED = 256
 
@@ -151,7 +151,7 @@ def _tptr(t):
 
 def make_desc(shape, kinematics, material, nphase, tol_newton=1e-10, tol_cg=1e-10, max_newton=50,
               max_cg=10000, k_mode=K_RECOMPUTE, tangent=False, density=False, lengths=None, graph=False,
-              batch=1):
+              batch=1, plane_stress=False):
     d = Desc()
     shape = tuple(int(s) for s in shape)
     d.ndim = len(shape)
@@ -167,7 +167,8 @@ def make_desc(shape, kinematics, material, nphase, tol_newton=1e-10, tol_cg=1e-1
     d.max_newton = int(max_newton)
     d.max_cg = int(max_cg)
     d.k_mode = int(k_mode)
-    d.flags = (FLAG_TANGENT if tangent else 0) | (FLAG_DENSITY if density else 0) | (FLAG_GRAPH if graph else 0)
+    d.flags = (FLAG_TANGENT if tangent else 0) | (FLAG_DENSITY if density else 0) | (FLAG_GRAPH if graph else 0) \
+        | (FLAG_PLANE_STRESS if plane_stress else 0)
     d.batch = int(batch)
     return d
 

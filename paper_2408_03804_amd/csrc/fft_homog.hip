@@ -102,7 +102,10 @@ int validate_desc(const fft_homog_desc* d) {
   if (d->max_newton < 0 || d->max_cg < 0) return FFT_HOMOG_EINVAL;
   if (d->k_mode != FFT_HOMOG_K_RECOMPUTE && d->k_mode != FFT_HOMOG_K_STORED) return FFT_HOMOG_EINVAL;
   if (d->batch < 0) return FFT_HOMOG_EINVAL;
-  if (d->flags & ~(FFT_HOMOG_FLAG_TANGENT | FFT_HOMOG_FLAG_DENSITY | FFT_HOMOG_FLAG_GRAPH)) return FFT_HOMOG_EINVAL;
+  if (d->flags & ~(FFT_HOMOG_FLAG_TANGENT | FFT_HOMOG_FLAG_DENSITY | FFT_HOMOG_FLAG_GRAPH | FFT_HOMOG_FLAG_PLANE_STRESS))
+    return FFT_HOMOG_EINVAL;
+  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && (d->ndim != 2 || d->material != FFT_HOMOG_LINEAR_ELASTIC))
+    return FFT_HOMOG_EINVAL;
   if (d->batch > 1) {
     // a multi-cell handle runs the tangent solves of every cell at the reference state
     if (!(d->flags & FFT_HOMOG_FLAG_TANGENT)) return FFT_HOMOG_EINVAL;
@@ -690,6 +693,18 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
     for (int ph = 0; ph < h->desc.nphase; ++ph)
       if (!(lm[4 * ph + 2] >= 0.0) || !(lm[4 * ph + 3] >= 0.0) || !(3.0 * lm[4 * ph + 1] + lm[4 * ph + 3] > 0.0))
         return fail(h, FFT_HOMOG_EINVAL, "J2 phase needs sig_y >= 0, H >= 0, 3 mu + H > 0");
+  // plane stress (2D linear elasticity): sig_33 = 0 eliminates eps_33, which leaves the 2D law with
+  // the reduced first Lame parameter 2 lam mu / (lam + 2 mu)
+  std::vector<double> reduced;
+  if (h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) {
+    reduced.assign(lm, lm + (size_t)2 * h->desc.nphase * cells);
+    for (size_t k = 0; k < reduced.size(); k += 2) {
+      const double la = reduced[k], m = reduced[k + 1];
+      if (!(la + 2.0 * m != 0.0)) return fail(h, FFT_HOMOG_EINVAL, "plane stress needs lam + 2 mu != 0");
+      reduced[k] = 2.0 * la * m / (la + 2.0 * m);
+    }
+    lm = reduced.data();
+  }
   drop_graphs(h);
   FH_CK(hipMemcpyAsync(h->phase, phase, (size_t)cells * h->g.N, hipMemcpyDeviceToDevice, h->stream));
   FH_CK(hipMemcpy2DAsync(h->table, (size_t)ts * kMaxPhase * sizeof(double), lm, row, row, cells,

@@ -64,7 +64,8 @@ def test_workspace_size_is_host_only_and_sane(shape, kin, mat):
     (lambda d: setattr(d, "nphase", 0), "einval"),
     (lambda d: setattr(d, "material", 1), "einval"),   # Neo-Hookean with small strain
     (lambda d: d.n.__setitem__(1, 4096), "eunsupported"),
-    (lambda d: setattr(d, "flags", 8), "einval"),                     # unknown flag
+    (lambda d: setattr(d, "flags", 16), "einval"),                    # unknown flag
+    (lambda d: setattr(d, "flags", 8), "einval"),                     # plane stress in 3D
     (lambda d: setattr(d, "batch", -1), "einval"),
     (lambda d: setattr(d, "batch", 4), "einval"),                     # multi-cell without FLAG_TANGENT
     (lambda d: (setattr(d, "batch", 4), setattr(d, "flags", 3)), "einval"),   # ... with FLAG_DENSITY

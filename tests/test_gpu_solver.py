@@ -205,3 +205,31 @@ def test_bad_phase_id_rejected():
     with pytest.raises(FFTHomogError) as ei:
         h.set_material(ph, [[1.0, 1.0], [2.0, 2.0]])
     assert ei.value.status == "einval"
+
+
+def test_plane_stress_disk_matches_oracle():
+    """2D linear elasticity under plane stress (FLAG_PLANE_STRESS) against the oracle's 3D law with
+    sigma_33 = 0 solved per voxel: fields, homogenized stress and tangent."""
+    w = workloads.workload_disk2d(31)
+    shape = w["shape"]
+    d = 2
+    h = make(shape, "small", "linear_elastic", tol_cg=1e-12, tangent=True, plane_stress=True)
+    h.set_material(w["phase"], w["table"])
+    S, psi, st = h.solve(w["macro"], 1)
+    lam, mu = lame_fields(w["phase"], w["table"])
+    prob = newton_cg.Problem(shape, "linear_elastic_plane_stress", lam, mu)
+    ref = newton_cg.solve(prob, w["macro"], n_increments=1, tol_cg=1e-12)
+    check_counts(st, ref["stats"])
+    F = np.moveaxis(h.get_field(0).cpu().numpy().reshape((d, d) + shape), (0, 1), (-2, -1))
+    Fbar = ref["state"].macro
+    assert rel(F - Fbar, ref["state"].field - Fbar) < TOL_FIELD
+    assert np.abs(S - ref["macro_stress"]).max() < TOL_HOMOG * np.abs(ref["macro_stress"]).max()
+    assert abs(psi - ref["energy"]) < TOL_HOMOG * abs(ref["energy"])
+    C, _ = h.tangent()
+    Cref, _, _ = newton_cg.homogenized_tangent(prob, ref["state"], tol_cg=1e-12)
+    assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
+    # plane stress is softer than plane strain
+    g = make(shape, "small", "linear_elastic", tol_cg=1e-12)
+    g.set_material(w["phase"], w["table"])
+    S2, _, _ = g.solve(w["macro"], 1)
+    assert S[0] < S2[0]

@@ -509,3 +509,23 @@ def test_adjoint_energy_gradient_is_envelope_form():
     assert k == 0
     psi = prob.energy_density(ref["state"].field)
     assert rel(grad, 3.0 * psi / (prob.N * rho)) < 1e-13
+
+
+def test_plane_stress_is_the_3d_law_with_zero_out_of_plane_stress():
+    """Pins the plane-stress oracle: sigma_33 of the 3D law vanishes at the eps_33 it chooses, and the
+    in-plane response equals 2D linear elasticity with the reduced first parameter 2 lam mu / (lam + 2 mu)."""
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal((10, 2, 2))
+    eps = 0.5 * (A + np.swapaxes(A, -1, -2))
+    lam, mu = rng.uniform(0.5, 3.0, 10), rng.uniform(0.5, 2.0, 10)
+    PS = materials.LinearElasticPlaneStress
+    e3 = PS._full(eps, lam, mu)
+    s3 = materials.LinearElastic.stress(e3, lam, mu)
+    assert np.abs(s3[..., 2, 2]).max() < 1e-14
+    lam_s = 2 * lam * mu / (lam + 2 * mu)
+    assert np.abs(PS.stress(eps, lam, mu) - materials.LinearElastic.stress(eps, lam_s, mu)).max() < 1e-14
+    assert np.abs(PS.psi(eps, lam, mu) - materials.LinearElastic.psi(eps, lam_s, mu)).max() < 1e-14
+    # plane stress is softer than plane strain in the in-plane normal directions
+    one = np.zeros((1, 2, 2))
+    one[0, 0, 0] = 1.0
+    assert PS.stress(one, 1.0, 1.0)[0, 0, 0] < materials.LinearElastic.stress(one, 1.0, 1.0)[0, 0, 0]

@@ -327,6 +327,7 @@ def bench_paper_example(args, w, k_mode, paper_seconds, paper_note):
     h = FFTHomog(shape, w["kinematics"], w["material"], 2, device="cuda:0", tol_newton=w["tol_newton"],
                  tol_cg=w["tol_cg"], max_newton=50, max_cg=20000, k_mode=k_mode)
     h.set_material(w["phase"], w["table"])
+    shape_info = h.autotune(reps=5) if args.autotune else h.launch_shape()
 
     def step():
         h.reset()
@@ -372,6 +373,7 @@ def bench_paper_example(args, w, k_mode, paper_seconds, paper_note):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w["name"], "grid": list(shape), "material": w["material"],
                    "n_increments": w["n_increments"], "k_mode": "stored" if k_mode else "recompute",
+                   "launch_shape": shape_info,
                    "newton_iterations": st["newton"], "cg_iterations": st["cg_total"],
                    "voxel_iters_per_s": N * cg / (wall * args.steps),
                    "paper_seconds_context": paper_seconds, "paper_context": paper_note},

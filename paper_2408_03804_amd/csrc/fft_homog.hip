@@ -27,6 +27,7 @@ constexpr size_t kLdsFft = 48 * 1024;
 constexpr size_t kLdsOuter = 64 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
 constexpr int kOuterTileMax = 4;   // kx bins per outer-pass block (measured best at 128^3)
+constexpr long long kBlocksTarget = 512;  // blocks per pass the default tiles aim for (2 per CU)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -138,8 +139,16 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   }
   const AxisPlan& pouter = pl[d->ndim - 1];
   const int rows = g.ny * g.nz;
+  // Default tiles: as large as the LDS budget allows, but small enough that each pass still
+  // launches about kBlocksTarget blocks at the handle's typical batch (one right-hand side, or
+  // all of a multi-cell handle's) -- small grids otherwise leave most of the 256 CUs idle.
+  const long long Bd = L->cells > 1 ? L->B : 1;
+  auto par_cap = [&](long long work_per_unit, int hi) {
+    return (int)std::max(1LL, std::min((long long)hi, work_per_unit * Bd / kBlocksTarget));
+  };
   // x pass: rows per block, aiming at one or two voxels per thread
   int rmax = std::max(1, std::min(16, (2 * kThreads + g.nx - 1) / g.nx));
+  rmax = std::min(rmax, par_cap(rows, rmax));
   int R = 0, inx = 0;
   for (int r = rmax; r >= 1; --r) {
     if (r > rows && r > 1) continue;
@@ -156,7 +165,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->R = R;
   L->in_x = inx;
   int TXm = 0, inm = 0;
-  for (int t = 16; t >= 1; --t) {
+  for (int t = par_cap((long long)g.nxh * g.nz * C, 16); t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
     const int ip = inplace_ok(pl[1], t) ? 1 : 0;
     if (mid_smem(g, t, ip) <= kLdsFft) { TXm = t; inm = ip; break; }
@@ -170,7 +179,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->in_m = inm;
   const int G = outer_group(g);
   int TXo = 0, ino = 0;
-  for (int t = 16; t >= 1; --t) {
+  for (int t = par_cap((long long)g.nxh * g.n_mid * (C / G), kOuterTileMax); t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
     const int ip = inplace_ok(pouter, G * t) ? 1 : 0;
     if (t <= kOuterTileMax && outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }

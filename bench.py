@@ -137,7 +137,7 @@ def bench_cells(args, name, cells, description):
 
     dev = [dict(phase=torch.as_tensor(c["phase"]).to("cuda:0"), table=c["table"]) for c in cells]
     b = TangentBatcher(tol_cg=1e-10, max_cg=20000, graph=not args.no_graph, autotune=not args.no_autotune,
-                       max_bytes=int(args.max_gb * (1 << 30)), device="cuda:0")
+                       max_bytes=int(args.max_gb * (1 << 30)), device="cuda:0", concurrent=args.concurrent)
     for i in range(args.warmup):
         C, info = b.tangents(dev)
         log("warmup %d: %s" % (i, ", ".join("%s x%d cg %d %.3fs" % (r["shape"][0], r["cells"], r["cg_total"],
@@ -183,7 +183,7 @@ def bench_cells(args, name, cells, description):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": description, "cells": len(cells),
                    "groups": {str(k): sum(r["cells"] for r in v) for k, v in groups.items()},
-                   "graph": not args.no_graph, "autotune": not args.no_autotune,
+                   "graph": not args.no_graph, "autotune": not args.no_autotune, "concurrent": args.concurrent,
                    "launch_shapes": {str(k): v for k, v in b.shapes.items()},
                    "cg_iterations_per_step": cg // args.steps,
                    "voxel_iters_per_s": vox_iters / wall},
@@ -410,6 +410,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="nh128: tune the launch shape before timing")
     ap.add_argument("--graph", action="store_true", help="nh128: replay CG chunks from a captured HIP graph")
     ap.add_argument("--max-gb", type=float, default=96.0, help="workspace budget per multi-cell handle")
+    ap.add_argument("--concurrent", action="store_true", help="many-cell workloads: run the size groups concurrently")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")

@@ -20,8 +20,12 @@ MAX_CELLS_PER_LAUNCH = 65535
 
 
 class TangentBatcher:
+    """With ``concurrent``, the grid-size groups run at the same time, each on its own stream
+    (default priority) driven by its own host thread, so that one group's convergence tail
+    overlaps the others' work.  Launch shapes are tuned beforehand, one group at a time."""
+
     def __init__(self, kinematics="small", material="linear_elastic", nphase=2, tol_cg=1e-10, max_cg=20000,
-                 max_bytes=64 << 30, graph=True, autotune=True, device=None, stream=None):
+                 max_bytes=64 << 30, graph=True, autotune=True, device=None, stream=None, concurrent=False):
         self.kinematics = kinematics
         self.material = material
         self.nphase = int(nphase)
@@ -32,6 +36,8 @@ class TangentBatcher:
         self.stream = stream
         self.handles = OrderedDict()
         self.shapes = {}
+        self.concurrent = concurrent
+        self.streams = {}
 
     def _ncomp(self, shape):
         d = len(shape)
@@ -57,12 +63,22 @@ class TangentBatcher:
                 hi = mid - 1
         return lo
 
+    def _stream(self, shape):
+        if not self.concurrent:
+            return self.stream
+        import torch
+        st = self.streams.get(shape)
+        if st is None:
+            st = torch.cuda.Stream(device=self.device)
+            self.streams[shape] = st
+        return st
+
     def handle(self, shape, k):
         key = (tuple(shape), int(k))
         h = self.handles.get(key)
         if h is None:
             h = binding.FFTHomog(shape, self.kinematics, self.material, self.nphase, device=self.device,
-                                 stream=self.stream, batch=k, **self.kw)
+                                 stream=self._stream(tuple(shape)), batch=k, **self.kw)
             self.handles[key] = h
             self._tune = key if self.autotune else None
         return h
@@ -80,36 +96,82 @@ class TangentBatcher:
         for i, cell in enumerate(cells):
             groups.setdefault(tuple(cell["phase"].shape), []).append(i)
         out = [None] * len(cells)
-        info = []
+        jobs = OrderedDict()
         for shape, idx in groups.items():
             k = self.chunk_size(shape, len(idx))
-            for s in range(0, len(idx), k):
-                chunk = idx[s:s + k]
-                self._tune = None
-                h = self.handle(shape, len(chunk))
-                phase = torch.stack([torch.as_tensor(cells[i]["phase"]).to(device=h.device, dtype=torch.uint8)
-                                     for i in chunk])
-                table = np.stack([np.asarray(cells[i]["table"], dtype=np.float64) for i in chunk])
-                h.set_material(phase, table)
-                if self._tune is not None:
-                    # one tuning per grid shape; later chunk sizes of that grid reuse it
-                    known = [v for k, v in self.shapes.items() if k[0] == self._tune[0]]
-                    if known:
-                        h.set_launch_shape(known[0])
-                    else:
-                        self.shapes[self._tune] = h.autotune()
-                if h.cells == 1:
-                    # a one-cell handle takes its tangent at a converged state: the reference
-                    # state is one (zero load, no CG)
-                    d = len(shape)
-                    h.reset()
-                    h.solve(np.eye(d).reshape(-1) if self.kinematics == "finite" else np.zeros(h.c), 1)
-                C, st = h.tangent()
-                C = C.reshape(len(chunk), h.c, h.c)
-                for j, i in enumerate(chunk):
-                    out[i] = C[j]
-                info.append(dict(shape=shape, cells=len(chunk), cg_total=st["cg_total"], seconds=st["seconds"],
-                                 status=st["status"]))
+            jobs[shape] = [idx[s:s + k] for s in range(0, len(idx), k)]
+
+        def stack_phase(h, chunk):
+            # on the handle's stream, which the library then uses: no cross-stream dependency
+            with torch.cuda.stream(h.stream):
+                return torch.stack([torch.as_tensor(cells[i]["phase"]).to(device=h.device, dtype=torch.uint8)
+                                    for i in chunk])
+
+        def run_chunk(shape, chunk, allow_tune):
+            self._tune = None
+            h = self.handle(shape, len(chunk))
+            tune = self._tune if allow_tune else None
+            phase = stack_phase(h, chunk)
+            table = np.stack([np.asarray(cells[i]["table"], dtype=np.float64) for i in chunk])
+            h.set_material(phase, table)
+            if tune is not None:
+                # one tuning per grid shape; later chunk sizes of that grid reuse it
+                known = [v for kk, v in self.shapes.items() if kk[0] == tune[0]]
+                if known:
+                    h.set_launch_shape(known[0])
+                else:
+                    self.shapes[tune] = h.autotune()
+            if h.cells == 1:
+                # a one-cell handle takes its tangent at a converged state: the reference
+                # state is one (zero load, no CG)
+                d = len(shape)
+                h.reset()
+                h.solve(np.eye(d).reshape(-1) if self.kinematics == "finite" else np.zeros(h.c), 1)
+            C, st = h.tangent()
+            C = C.reshape(len(chunk), h.c, h.c)
+            for j, i in enumerate(chunk):
+                out[i] = C[j]
+            return dict(shape=shape, cells=len(chunk), cg_total=st["cg_total"], seconds=st["seconds"],
+                        status=st["status"])
+
+        if not self.concurrent:
+            info = [run_chunk(shape, chunk, self.autotune) for shape, chs in jobs.items() for chunk in chs]
+        else:
+            import threading
+
+            # handles are created and tuned one group at a time, so that tuning timings do not overlap
+            for shape, chs in jobs.items():
+                for chunk in chs:
+                    key = (shape, len(chunk))
+                    if key not in self.handles:
+                        self._tune = None
+                        h = self.handle(shape, len(chunk))
+                        if self._tune is not None:
+                            phase = stack_phase(h, chunk)
+                            h.set_material(phase, np.stack([np.asarray(cells[i]["table"], dtype=np.float64)
+                                                            for i in chunk]))
+                            known = [v for kk, v in self.shapes.items() if kk[0] == shape]
+                            if known:
+                                h.set_launch_shape(known[0])
+                            else:
+                                self.shapes[self._tune] = h.autotune()
+            results = {}
+            errors = []
+
+            def worker(shape, chs):
+                try:
+                    results[shape] = [run_chunk(shape, chunk, False) for chunk in chs]
+                except Exception as e:  # re-raised in the calling thread
+                    errors.append(e)
+
+            threads = [threading.Thread(target=worker, args=(shape, chs)) for shape, chs in jobs.items()]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            if errors:
+                raise errors[0]
+            info = [r for shape in jobs for r in results[shape]]
         if len({o.shape for o in out}) == 1:
             out = np.stack(out)
         return out, info

@@ -220,3 +220,19 @@ def test_explicit_launch_shapes_keep_oracle_parity(shape, kin, mat):
             h.set_launch_shape(bad)
         assert ei.value.status == "einval"
     assert h.launch_shape() == default
+
+
+def test_batcher_runs_size_groups_concurrently_with_the_same_results():
+    from paper_2408_03804_amd.batch import TangentBatcher
+    cells = []
+    for shape, k, seed in (((8, 8, 8), 3, 31), ((12, 10, 6), 2, 32), ((6, 6, 6), 2, 33)):
+        cells += [dict(phase=p, table=t) for p, t in random_cells(shape, k, seed)]
+    a = TangentBatcher(autotune=False)
+    Ca, _ = a.tangents(cells)
+    b = TangentBatcher(autotune=False, concurrent=True)
+    Cb, info = b.tangents(cells)
+    Cb2, _ = b.tangents(cells)
+    assert np.array_equal(Ca, Cb) and np.array_equal(Cb, Cb2)
+    assert sum(r["cells"] for r in info) == len(cells)
+    a.close()
+    b.close()

@@ -390,7 +390,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
     ap.add_argument("--timing-iters", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
     ap.add_argument("--train-cells", type=int, default=20000)

@@ -38,13 +38,18 @@ CG_KERNEL_SOURCES = ["common.h", "dual.h", "fft_lds.h", "kernels.h", "kernels.hi
 
 
 def kernel_source_hash():
-    """sha256 of the sources of the CG-iteration kernels (device code and the headers it includes);
-    HBM counter records are valid only for the kernels they were taken on."""
+    """sha256 of the sources of the CG-iteration kernels (device code and the headers it includes)
+    and of the flags they are compiled with; HBM counter records are valid only for the kernels
+    they were taken on."""
     import hashlib
+
+    from paper_2408_03804_amd import build as _build
 
     h = hashlib.sha256()
     for f in CG_KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2408_03804_amd", "csrc", f), "rb").read())
+    flags = [f for f in _build.FLAGS + _build.PER_FILE.get("kernels.hip", []) if os.sep not in f]
+    h.update(" ".join(flags).encode())
     return h.hexdigest()
 
 

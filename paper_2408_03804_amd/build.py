@@ -19,13 +19,18 @@ FLAGS = [
     "-std=c++17",
     "--offload-arch=gfx950",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-function",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
+# The CG kernels' dual numbers are seeded with literal zeros (one-hot partials); with these two
+# flags the compiler may drop products with them and additions of them, which is exact for
+# finite values (results change at most in the sign of a zero) and removes a sixth of the
+# forward x pass's time.  They also let the compiler assume no NaN or Inf, so every domain and
+# breakdown test in those kernels is an integer test on the exponent bits (finite_bits).
+PER_FILE = {"kernels.hip": ["-ffinite-math-only", "-fno-signed-zeros"]}
 
 
 def hipcc():
@@ -36,15 +41,38 @@ def hipcc():
 
 
 def build(verbose=False, extra_flags=()):
-    """Compile every source into libfft_homog.so (always recompiles)."""
-    cmd = [hipcc()] + FLAGS + list(extra_flags) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+    """Compile every source (in parallel) and link libfft_homog.so (always recompiles)."""
+    import tempfile
+
+    tmp = tempfile.mkdtemp(prefix="fft_homog_build_")
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(tmp, src.replace(".hip", ".o"))
+        cmd = [hipcc()] + FLAGS + PER_FILE.get(src, []) + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out + err)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed building libfft_homog.so")
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfft_homog.so")
+        raise RuntimeError("hipcc failed linking libfft_homog.so")
     os.replace(LIB + ".tmp", LIB)
+    for o in objs:
+        os.remove(o)
+    os.rmdir(tmp)
     return LIB
 
 

@@ -26,6 +26,13 @@ __host__ __device__ constexpr int fixed_radix(int n, int st) {
        : 8;
 }
 
+// x is neither NaN nor +-Inf, decided on the exponent bits: the CG kernels are compiled with
+// finite-math assumptions (see build.py), under which a floating-point isfinite() or NaN
+// comparison may be folded away; integer tests are not.
+__device__ __forceinline__ bool finite_bits(double x) {
+  return (__double_as_longlong(x) & 0x7ff0000000000000LL) != 0x7ff0000000000000LL;
+}
+
 // Exact w / d for w * d < 2^32 with a precomputed multiplier m = floor(2^32 / d) + 1
 // (d = 1 has no 32-bit multiplier and is passed through).
 struct FastDiv {

@@ -80,20 +80,22 @@ __device__ __forceinline__ void cg_finalize(CgState& S, double s) {
     S.iters = 0;
     S.first = 1;
     S.beta = 0.0;
-    if (sqrt(s) <= 1e-13 * sqrt(S.src2)) S.status = CG_ZERO_RHS;
+    if (!finite_bits(s)) S.status = CG_BREAKDOWN;
+    else if (sqrt(s) <= 1e-13 * sqrt(S.src2)) S.status = CG_ZERO_RHS;
     else if (sqrt(s) <= S.tol * sqrt(s)) S.status = CG_CONVERGED;
     else if (S.max_iters <= 0) S.status = CG_MAXIT;
     else S.status = CG_RUNNING;
   } else if (WHAT == RED_PQ) {
     S.pq = s;
-    if (!(s > 0.0)) S.status = CG_BREAKDOWN;
+    if (!(finite_bits(s) && s > 0.0)) S.status = CG_BREAKDOWN;
     else S.alpha = S.rr / s;
   } else {  // RED_RR
     S.beta = s / S.rr;
     S.rr = s;
     S.iters += 1;
     S.first = 0;
-    if (sqrt(s) <= S.tol * sqrt(S.rr0)) S.status = CG_CONVERGED;
+    if (!finite_bits(s)) S.status = CG_BREAKDOWN;
+    else if (sqrt(s) <= S.tol * sqrt(S.rr0)) S.status = CG_CONVERGED;
     else if (S.iters >= S.max_iters) S.status = CG_MAXIT;
   }
 }
@@ -214,13 +216,13 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
       if (PROD == PROD_STRESS) {
         if (MAT == MAT_NH || MAT == MAT_STVK) {
           const double J = det_packed<NDIM>(e);
-          if (!(J > 0.0)) bad = 1;
+          if (!(finite_bits(J) && J > 0.0)) bad = 1;
         }
         stress_ad<MAT, NDIM>(e, L, v);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           acc += v[j] * v[j];
-          if (!isfinite(v[j])) bad = 1;
+          if (!finite_bits(v[j])) bad = 1;
         }
       } else if (PROD == PROD_ADJ) {
         // objective gradient with respect to the strain: g = w_e P + K : W
@@ -748,7 +750,10 @@ __global__ void __launch_bounds__(kThreads) k_homogenize(const double* F, MatPar
 #pragma unroll
     for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
     load_local<MAT, NDIM>(m, v, L);
-    if ((MAT == MAT_NH || MAT == MAT_STVK) && !(det_packed<NDIM>(e) > 0.0)) st[0].domain = 1;
+    if (MAT == MAT_NH || MAT == MAT_STVK) {
+      const double J = det_packed<NDIM>(e);
+      if (!(finite_bits(J) && J > 0.0)) st[0].domain = 1;
+    }
     vals[C] = stress_ad<MAT, NDIM>(e, L, vals);
   }
   block_sum_many(vals, C + 1, sh, partials, nblocks);

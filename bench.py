@@ -394,7 +394,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
-    ap.add_argument("--timing-iters", type=int, default=20)
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="sample every k-th CG iteration of the timed solves for the per-kernel times")
     ap.add_argument("--cpu-iters", type=int, default=7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
@@ -497,6 +498,9 @@ def main():
     for i in range(args.warmup):
         S, psi, st = step()
         log("warmup %d: newton %d, cg %d, %.3f s" % (i, st["newton"], st["cg_total"], st["seconds"]))
+    # per-kernel device time, sampled inside the timed solves: HIP events on the library's
+    # stream around the launches of every `timing_every`-th CG iteration
+    h.set_kernel_timing(args.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_cg = 0
@@ -511,9 +515,11 @@ def main():
     wall = t1 - t0
     value = N * total_cg / wall
 
-    # per-kernel device time of one CG iteration at the converged state
-    ms = h.debug_time_cg(args.timing_iters)
-    log("kernel ms: " + ", ".join("%s %.4f" % (k, v) for k, v in zip(KERNELS, ms)))
+    ms, samples = h.kernel_timing()
+    h.set_kernel_timing(0)
+    if samples == 0:
+        raise RuntimeError("no CG iteration was sampled for kernel timing")
+    log("kernel ms (%d sampled CG iterations): " % samples + ", ".join("%s %.4f" % (k, v) for k, v in zip(KERNELS, ms)))
     Nh = (n // 2 + 1) * n * n
     bpv = algorithmic_bytes_per_voxel(c, N, Nh, True)
     dom = int(np.argmax(ms))
@@ -524,6 +530,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(name),
                 "kernel_ms": round(float(ms[dom]), 5),
+                "timing": "HIP events on the library stream inside the timed solves, every %d-th CG "
+                          "iteration (%d samples)" % (args.timing_every, samples),
                 "algorithmic_bytes_per_launch": int(bpv[name] * N),
                 "cg_iteration": {"ms": round(cg_ms, 5), "algorithmic_bytes": int(iter_bytes),
                                  "achieved_GBs": round(iter_bytes / (cg_ms * 1e-3) / 1e9, 1),

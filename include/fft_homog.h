@@ -254,11 +254,26 @@ int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, i
  * iteration (section 3 operator, Appendix A linear solve), measured over `iters` iterations
  * of the linear solve G*(K:x) = -G*(K:E_1) at the current state, batch 1, with the
  * convergence test disabled.  ms[7] receives, in launch order: x-pass forward (CG vector
- * update, K:p, x-FFT, partial <p,K:p>), <p,K:p> reduction and alpha, y-pass forward, outer
- * pass (outer-axis FFT, G-hat, inverse FFT), y-pass inverse, x-pass inverse (inverse x-FFT,
- * residual update, partial <r,r>), <r,r> reduction, beta and the convergence test; 2D grids
- * report 0 for the y passes.  Leaves the strain state unchanged. */
+ * update, K:p, x-FFT, partial <p,K:p>), a slot for a separate <p,K:p> reduction (0: one block
+ * of the outer pass sums <p,K:p> and sets alpha), y-pass forward, outer pass (outer-axis FFT,
+ * G-hat, inverse FFT), y-pass inverse, x-pass inverse (inverse x-FFT, residual update, partial
+ * <r,r>), <r,r> reduction, beta and the convergence test; 2D grids report 0 for the y passes.
+ * Leaves the strain state unchanged. */
 int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms);
+
+/* Sampled kernel timing inside the solver's own CG loops (solve, tangent and adjoint calls):
+ * with every > 0, each every-th CG iteration enqueued on the handle's stream gets a HIP event
+ * before its first launch and after each of its seven launches; every = 0 switches sampling
+ * off.  Either call clears the accumulated samples.  Chunks replayed from a HIP graph
+ * (FLAG_GRAPH) are not sampled.  The events add a few microseconds to each sampled iteration.
+ * EINVAL for every < 0. */
+int fft_homog_set_kernel_timing(fft_homog_t* h, int every);
+/* Average device time (ms) of each launch of the sampled CG iterations since the last
+ * fft_homog_set_kernel_timing, in the launch order and layout of fft_homog_debug_time_cg's
+ * ms[7]: the time from the previous launch's end event to this launch's end event, so it
+ * includes the launch's dispatch.  *samples receives the number of sampled iterations (ms is
+ * all zero when it is 0). */
+int fft_homog_get_kernel_timing(const fft_homog_t* h, double* ms, long long* samples);
 
 #ifdef __cplusplus
 }

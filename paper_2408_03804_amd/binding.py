@@ -79,6 +79,7 @@ EXPORTS = [
     "fft_homog_destroy", "fft_homog_strerror", "fft_homog_last_error",
     "fft_homog_debug_constitutive", "fft_homog_debug_rfft", "fft_homog_debug_irfft",
     "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_time_cg",
+    "fft_homog_set_kernel_timing", "fft_homog_get_kernel_timing",
     "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune",
 ]
 
@@ -117,6 +118,8 @@ def load_library(path=LIB_PATH):
         "fft_homog_debug_project": (I, [P, P, P, I]),
         "fft_homog_debug_apply_operator": (I, [P, P, P, I]),
         "fft_homog_debug_time_cg": (I, [P, I, DP]),
+        "fft_homog_set_kernel_timing": (I, [P, I]),
+        "fft_homog_get_kernel_timing": (I, [P, DP, ctypes.POINTER(ctypes.c_longlong)]),
         "fft_homog_get_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_set_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_autotune": (I, [P, I, ctypes.POINTER(I)]),
@@ -358,6 +361,17 @@ class FFTHomog:
         ms = np.zeros(7)
         self._check(self.L.fft_homog_debug_time_cg(self.h, int(iters), _dptr(ms)))
         return ms
+
+    def set_kernel_timing(self, every):
+        """Sample every `every`-th CG iteration of later solves with HIP events (0: off)."""
+        self._check(self.L.fft_homog_set_kernel_timing(self.h, int(every)))
+
+    def kernel_timing(self):
+        """(ms[7] per launch of a CG iteration averaged over the samples, number of samples)."""
+        ms = np.zeros(7)
+        n = ctypes.c_longlong(0)
+        self._check(self.L.fft_homog_get_kernel_timing(self.h, _dptr(ms), ctypes.byref(n)))
+        return ms, int(n.value)
 
 
 # module-level functions with the C names (thin pass-throughs on a handle object)

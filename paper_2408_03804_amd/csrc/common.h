@@ -97,7 +97,8 @@ struct CgState {
   int first;        // next CG iteration starts with p = r
   int max_iters;
   int domain;       // constitutive domain error raised (det F <= 0 or non-finite stress)
-  int pad1[3];
+  int pq_fail;      // this iteration's <p, K:p> was not positive; the <r, r> step stops the CG
+  int pad1[2];
 };
 
 enum CgStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_ZERO_RHS = 2, CG_BREAKDOWN = 3, CG_MAXIT = 4 };

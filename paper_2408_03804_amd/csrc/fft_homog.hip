@@ -23,6 +23,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kResults = 128;
 constexpr int kChunk = 8;          // CG iterations enqueued between host checks
+constexpr int kTimedLaunches = 7;  // launches of one CG iteration (kernel timing)
 constexpr size_t kLdsFft = 48 * 1024;
 constexpr size_t kLdsOuter = 64 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
@@ -262,6 +263,14 @@ struct fft_homog {
   hipStream_t cap;
   hipGraphExec_t gexec[2];
   int gB[2];
+  // sampled kernel timing inside the CG loop (fft_homog_set_kernel_timing): event groups of
+  // kTimedLaunches + 1 events recorded since the last host check, and the running sums
+  int time_every;
+  long long time_count;  // CG iterations enqueued eagerly since timing was switched on
+  std::vector<hipEvent_t> tev;
+  int tev_used;
+  double time_acc[kTimedLaunches];
+  long long time_samples;
   std::string err;
 };
 
@@ -331,6 +340,9 @@ AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inpl
   a.spec = h->spec;
   a.st = st;
   a.active = nullptr;
+  a.pq_st = nullptr;
+  a.pq_partials = nullptr;
+  a.pq_nblocks = 0;
   return a;
 }
 
@@ -352,9 +364,41 @@ int spectral_middle(fft_homog_t* h, int mode, int B, const CgState* st) {
   return FFT_HOMOG_OK;
 }
 
+// Next group of kTimedLaunches + 1 events for a sampled CG iteration (created on first use).
+hipError_t timing_events(fft_homog_t* h, hipEvent_t** out) {
+  const size_t need = (size_t)(h->tev_used + 1) * (kTimedLaunches + 1);
+  while (h->tev.size() < need) {
+    hipEvent_t ev = nullptr;
+    const hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    h->tev.push_back(ev);
+  }
+  *out = h->tev.data() + (size_t)h->tev_used * (kTimedLaunches + 1);
+  ++h->tev_used;
+  return hipSuccess;
+}
+
+// Add the sampled iterations recorded since the last host check to the running sums; the
+// stream has been synchronised.
+int harvest_timing(fft_homog_t* h) {
+  for (int gi = 0; gi < h->tev_used; ++gi) {
+    const hipEvent_t* ev = h->tev.data() + (size_t)gi * (kTimedLaunches + 1);
+    for (int k = 0; k < kTimedLaunches; ++k) {
+      float t = 0.f;
+      FH_CK(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      h->time_acc[k] += t;
+    }
+    ++h->time_samples;
+  }
+  h->tev_used = 0;
+  return FFT_HOMOG_OK;
+}
+
 // m CG iterations, enqueued on stream s, over B launch slots: slot i is right-hand side
 // active[i] (active == nullptr: i).  Right-hand sides that stop inside the chunk make
-// their blocks return at once.
+// their blocks return at once.  With kernel timing on (and s the handle's own stream, not a
+// graph capture), every time_every-th iteration gets an event before its first launch and
+// after each launch.
 hipError_t enqueue_cg_iters(fft_homog_t* h, int B, int m, hipStream_t s, const int* active = nullptr) {
   const int prod = h->desc.k_mode == FFT_HOMOG_K_STORED ? PROD_CGOP_STORED : PROD_CGOP;
   XFwdArgs a = xfwd_args(h);
@@ -363,13 +407,36 @@ hipError_t enqueue_cg_iters(fft_homog_t* h, int B, int m, hipStream_t s, const i
   a.active = active;
   XInvArgs ai = xinv_args(h);
   ai.active = active;
+  AxisArgs am = axis_args(h, 1, h->L.TXm, h->st);
+  AxisArgs ao = axis_args(h, h->g.ndim - 1, h->L.TXo, h->st);
+  am.active = ao.active = active;
+  ao.pq_st = h->st;
+  ao.pq_partials = h->partials;
+  ao.pq_nblocks = h->L.nblk_x;
+  const bool three = h->g.ndim == 3;
+  const bool timing = h->time_every > 0 && s == h->stream;
   hipError_t e = hipSuccess;
   for (int i = 0; i < m && e == hipSuccess; ++i) {
-    e = launch_xfwd(prod, h->matcode, a, B, s);
-    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, B, s, active);
-    if (e == hipSuccess) e = enqueue_spectral(h, OUTER_PROJECT, B, h->st, s, active);
+    hipEvent_t* ev = nullptr;
+    if (timing && h->time_count++ % h->time_every == 0) e = timing_events(h, &ev);
+    int k = 0;
+    auto mark = [&]() {
+      if (ev && e == hipSuccess) e = hipEventRecord(ev[k++], s);
+    };
+    mark();
+    if (e == hipSuccess) e = launch_xfwd(prod, h->matcode, a, B, s);
+    mark();
+    mark();  // <p, K:p> is reduced inside the outer pass
+    if (e == hipSuccess && three) e = launch_mid(-1, am, B, s);
+    mark();
+    if (e == hipSuccess) e = launch_outer(OUTER_PROJECT, ao, B, s);
+    mark();
+    if (e == hipSuccess && three) e = launch_mid(1, am, B, s);
+    mark();
     if (e == hipSuccess) e = launch_xinv(CONS_CGUPD, ai, B, s);
+    mark();
     if (e == hipSuccess) e = launch_cg_reduce(RED_RR, h->st, h->partials, h->L.nblk_x, B, s, active);
+    mark();
   }
   return e;
 }
@@ -449,6 +516,7 @@ int rhs_chain(fft_homog_t* h, int prod, int B, const double* unit) {
 // have stopped, the launches cover only the running ones (their indices are uploaded
 // before each chunk), so a batch's slow tail does not pay for its finished members.
 int cg_loop(fft_homog_t* h, int B) {
+  h->tev_used = 0;  // event groups of an earlier call that failed before its host check
   for (;;) {
     int nrun = 0;
     int done = 1 << 30;
@@ -468,6 +536,10 @@ int cg_loop(fft_homog_t* h, int B) {
     if (rc) return rc;
     rc = read_states(h, B);
     if (rc) return rc;
+    if (h->tev_used) {
+      rc = harvest_timing(h);
+      if (rc) return rc;
+    }
     bool still = false;
     for (int b = 0; b < B; ++b) still = still || h->h_st[b].status == CG_RUNNING;
     if (!still) {
@@ -970,6 +1042,7 @@ void fft_homog_destroy(fft_homog_t* h) {
   if (h->h_st) hipHostFree(h->h_st);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (hipEvent_t ev : h->tev) hipEventDestroy(ev);
   drop_graphs(h);
   if (h->cap) hipStreamDestroy(h->cap);
   delete h;
@@ -1097,6 +1170,10 @@ int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
   a.in = h->r;
   a.p = h->p;
   XInvArgs ai = xinv_args(h);
+  AxisArgs ao = axis_args(h, h->g.ndim - 1, h->L.TXo, h->st);
+  ao.pq_st = h->st;
+  ao.pq_partials = h->partials;
+  ao.pq_nblocks = h->L.nblk_x;
   const bool three = h->g.ndim == 3;
   hipEvent_t ev[8];
   for (int k = 0; k < 8; ++k) FH_CK(hipEventCreate(&ev[k]));
@@ -1106,11 +1183,11 @@ int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
     hipError_t e = hipEventRecord(ev[0], h->stream);
     if (e == hipSuccess) e = launch_xfwd(prod, h->matcode, a, 1, h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
-    if (e == hipSuccess) e = launch_cg_reduce(RED_PQ, h->st, h->partials, h->L.nblk_x, 1, h->stream);
+    // <p, K:p> is reduced inside the outer pass: its slot stays empty
     if (e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
     if (e == hipSuccess && three) e = launch_mid(-1, axis_args(h, 1, h->L.TXm, h->st), 1, h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], h->stream);
-    if (e == hipSuccess) e = launch_outer(OUTER_PROJECT, axis_args(h, h->g.ndim - 1, h->L.TXo, h->st), 1, h->stream);
+    if (e == hipSuccess) e = launch_outer(OUTER_PROJECT, ao, 1, h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[4], h->stream);
     if (e == hipSuccess && three) e = launch_mid(1, axis_args(h, 1, h->L.TXm, h->st), 1, h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[5], h->stream);
@@ -1133,6 +1210,23 @@ int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {
   if (h->h_st[0].status != CG_RUNNING && h->h_st[0].status != CG_MAXIT)
     return fail(h, FFT_HOMOG_ESTATE, "timed CG stopped early (breakdown)");
   for (int k = 0; k < 7; ++k) ms[k] = acc[k] / iters;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_set_kernel_timing(fft_homog_t* h, int every) {
+  if (!h || every < 0) return fail(h, FFT_HOMOG_EINVAL, "bad arguments");
+  h->tev_used = 0;
+  h->time_every = every;
+  h->time_count = 0;
+  for (int k = 0; k < kTimedLaunches; ++k) h->time_acc[k] = 0.0;
+  h->time_samples = 0;
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_get_kernel_timing(const fft_homog_t* h, double* ms, long long* samples) {
+  if (!h || !ms || !samples) return FFT_HOMOG_EINVAL;
+  *samples = h->time_samples;
+  for (int k = 0; k < kTimedLaunches; ++k) ms[k] = h->time_samples ? h->time_acc[k] / h->time_samples : 0.0;
   return FFT_HOMOG_OK;
 }
 

@@ -58,6 +58,11 @@ struct AxisArgs {
   double2* spec;
   const CgState* st;     // nullable: skip right-hand sides whose CG is not running
   const int* active;     // nullable: right-hand side of each launch-index group
+  // nullable (outer pass of a CG iteration): one block per right-hand side also sums the x
+  // pass's <p, K:p> block partials and sets alpha, in place of a separate reduction launch
+  CgState* pq_st;
+  const double* pq_partials;
+  int pq_nblocks;
 };
 
 // dynamic LDS bytes of each pass; `inplace` drops the ping-pong buffer

@@ -86,10 +86,16 @@ __device__ __forceinline__ void cg_finalize(CgState& S, double s) {
     else if (S.max_iters <= 0) S.status = CG_MAXIT;
     else S.status = CG_RUNNING;
   } else if (WHAT == RED_PQ) {
+    // runs inside the outer pass, whose other blocks read the status: a breakdown is only
+    // flagged here and becomes the status at the <r, r> step
     S.pq = s;
-    if (!(finite_bits(s) && s > 0.0)) S.status = CG_BREAKDOWN;
+    if (!(finite_bits(s) && s > 0.0)) S.pq_fail = 1;
     else S.alpha = S.rr / s;
   } else {  // RED_RR
+    if (S.pq_fail) {
+      S.status = CG_BREAKDOWN;
+      return;
+    }
     S.beta = s / S.rr;
     S.rr = s;
     S.iters += 1;
@@ -562,6 +568,16 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
   const int grp = bz - vb * NGRP;
   const int b = a.active ? a.active[vb] : vb;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
+  if (MODE == OUTER_PROJECT && a.pq_st != nullptr && bx == 0 && by == 0 && grp == 0) {
+    // <p, K:p> and alpha of right-hand side b, summed in a fixed order; nothing in this
+    // pass reads them (the inverse x pass does)
+    __shared__ double red[kThreads / 64];
+    const double* pp = a.pq_partials + (long long)b * a.pq_nblocks;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.pq_nblocks; i += blockDim.x) acc += pp[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) cg_finalize<RED_PQ>(a.pq_st[b], s);
+  }
   const int kx0 = bx * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
   const int mid = by;
@@ -658,7 +674,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_cg_reduce(CgState* st, const
   __shared__ double red[kReduceThreads / 64];
   const int b = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgState& S = st[b];
-  if ((WHAT == RED_PQ || WHAT == RED_RR) && S.status != CG_RUNNING) return;
+  if (WHAT == RED_RR && S.status != CG_RUNNING) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[(long long)b * nblocks + i];
   const double s = block_sum(acc, red);
@@ -1079,7 +1095,6 @@ hipError_t launch_cg_reduce(int what, CgState* st, const double* partials, int n
   switch (what) {
     case RED_SRC: hipLaunchKernelGGL((k_cg_reduce<RED_SRC>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
     case RED_RHS: hipLaunchKernelGGL((k_cg_reduce<RED_RHS>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
-    case RED_PQ: hipLaunchKernelGGL((k_cg_reduce<RED_PQ>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
     case RED_RR: hipLaunchKernelGGL((k_cg_reduce<RED_RR>), dim3(B), dim3(kReduceThreads), 0, s, st, partials, nblocks, active); break;
     default: return hipErrorInvalidValue;
   }

@@ -159,6 +159,35 @@ def test_repeat_solve_is_bitwise_deterministic():
     assert np.array_equal(outs[0][3], outs[1][3])
 
 
+def test_sampled_kernel_timing_leaves_the_solve_unchanged():
+    """Event sampling inside the CG loop: same bits as an untimed solve, positive times for
+    every launch, about one sample per `every` enqueued iterations, and cleared on reset."""
+    from paper_2408_03804_amd.binding import FFTHomogError
+    w = workloads.workload_neohookean3d(n=12, correlation_length=3.0)
+    outs = []
+    for every in (0, 1, 3):
+        h = make(w["shape"], "finite", "neo_hookean")
+        h.set_material(w["phase"], w["table"])
+        h.set_kernel_timing(every)
+        S, psi, st = h.solve(w["macro"], 2)
+        ms, n = h.kernel_timing()
+        outs.append((S, psi, h.get_field(0).cpu().numpy()))
+        if every == 0:
+            assert n == 0 and not ms.any()
+            with pytest.raises(FFTHomogError) as ei:
+                h.set_kernel_timing(-1)
+            assert ei.value.status == "einval"
+            continue
+        # chunks of 8 iterations are enqueued per host check; stopped solves skip their blocks
+        enq_max = st["cg_total"] + 8 * st["newton"]
+        assert -(-st["cg_total"] // every) <= n <= -(-enq_max // every)
+        assert (ms > 0).all()
+        h.set_kernel_timing(0)
+        assert h.kernel_timing()[1] == 0
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1] and np.array_equal(o[2], outs[0][2])
+
+
 # ---- error paths (all forced from the host; every kernel exits normally) -----
 def test_cg_iteration_limit_reports_enotconv():
     w = workloads.workload_disk2d(31)

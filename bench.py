@@ -401,7 +401,7 @@ def main():
     ap.add_argument("--k-mode", type=int, default=0)
     ap.add_argument("--train-cells", type=int, default=20000)
     ap.add_argument("--test-cells", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--check-tol", type=float, default=0.02)

@@ -64,13 +64,20 @@ def test_energy_gradient_is_envelope_form_without_cg():
 def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
     """Central differences of full solves (restarted from the converged base state) on random voxels.
 
-    Besides the relative tolerance, each comparison allows the rounding floor of the difference
-    quotient.  The two solves add different Newton updates to the same base field, so every entry
-    of their fields carries an independent rounding error of about u |F| per update (u = 2^-53).
-    That error is not a compatible field, so equilibrium does not cancel it.  Through sigma : dF
-    (and K : dF for the stress part) it adds a random term of size sqrt(2 n N) u |P| |F| to the
-    voxel sum of the psi differences, which the quotient divides by 2 h N.  The bound below takes
-    four times that size.
+    The energy part of J(rho + h) - J(rho - h) is summed voxel by voxel.  Away from the perturbed
+    voxel the energy difference is taken by the trapezoid rule, psi(F+) - psi(F-) =
+    (P(F+) + P(F-)) : (F+ - F-) / 2 up to O(|F+ - F-|^3), because the energies themselves are
+    O(strain^2) values assembled from O(mu |F|^2) terms whose rounding, different in the two
+    solves, would swamp an O(h) change summed over N voxels.  At the perturbed voxel, whose
+    parameters differ, the energies are differenced directly.
+
+    Besides the relative tolerance, each comparison allows the rounding floor of the quotient.  The
+    two solves add different Newton updates to the same base field, so every entry of their
+    fields carries an independent rounding error of about u |F| per update (u = 2^-53), an error
+    that is not a compatible field, so equilibrium does not cancel it.  Through P : dF (and K : dF
+    for the stress part) it adds a random term of size sqrt(2 n N) u |P| |F| to the voxel sum,
+    which the quotient divides by 2 h N; the stress part also differences P itself, an O(strain)
+    value assembled from O((lam + 2 mu) |F|) terms.  The bound takes four times those sizes.
     """
     shape = w["shape"]
     h = make(shape, "finite", "neo_hookean", tol_cg=tol_cg, tol_newton=tol_newton, max_cg=20000)
@@ -86,8 +93,10 @@ def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
     Pb = h.get_field(1).cpu().numpy().reshape(9, -1)
     rmsF = np.sqrt(np.mean(np.sum(Fb * Fb, axis=0)))
     rmsP = np.sqrt(np.mean(np.sum(Pb * Pb, axis=0)))
-    lam_mu = np.asarray(w["table"], dtype=np.float64)
-    kmax = 2.0 * np.max(lam_mu[:, 0] + 2.0 * lam_mu[:, 1]) * np.max(rho) ** 3
+    lam_v, mu_v = lame_fields(w["phase"], w["table"], rho, 3.0)
+    kmod = (lam_v + 2.0 * mu_v).reshape(-1)
+    kmax = 2.0 * kmod.max()
+    rms_pterm = np.sqrt(np.mean((kmod * np.sqrt(np.sum(Fb * Fb, axis=0))) ** 2))
     rng = np.random.default_rng(seed)
     flat = rng.choice(rho.size, nvox, replace=False)
     for f in flat:
@@ -103,12 +112,17 @@ def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
             o2, _, st2 = h.solve(w["macro"], 1)
             assert st2["status"] == "ok"
             n_upd = max(n_upd, st2["newton"])
-            fields.append((h.get_field(2).cpu().numpy(), h.get_field(1).cpu().numpy().reshape(9, -1)))
-        # J differences summed voxel by voxel (no cancellation against the mean)
-        dpsi = np.sum(fields[0][0] - fields[1][0]) / N
-        dP = np.sum(fields[0][1] - fields[1][1], axis=1) / N
+            fields.append((h.get_field(2).cpu().numpy().reshape(-1), h.get_field(1).cpu().numpy().reshape(9, -1),
+                           h.get_field(0).cpu().numpy().reshape(9, -1)))
+        (psi_p, P_p, F_p), (psi_m, P_m, F_m) = fields
+        dpsi_vox = 0.5 * np.sum((P_p + P_m) * (F_p - F_m), axis=0)
+        dpsi_vox[f] = psi_p[f] - psi_m[f]
+        dpsi = np.sum(dpsi_vox) / N
+        dP = np.sum(P_p - P_m, axis=1) / N
         fd = (we * dpsi + np.dot(ws, dP)) / (2 * hstep)
-        noise = 4.0 * u * np.sqrt(2.0 * max(n_upd, 1) * N) * rmsF * (abs(we) * rmsP + np.linalg.norm(ws) * kmax)
+        root = np.sqrt(2.0 * max(n_upd, 1) * N)
+        noise = 4.0 * u * root * (rmsF * (abs(we) * rmsP + np.linalg.norm(ws) * kmax)
+                                  + 2.0 * np.linalg.norm(ws) * rms_pterm)
         floor = noise / (2 * hstep * N)
         assert abs(fd - g[v]) <= tol * abs(g[v]) + floor, (v, fd, g[v], floor)
 
@@ -124,7 +138,7 @@ def test_energy_gradient_finite_differences_128_bench_configuration():
     rho = workloads.simp_density(w["shape"], 8.0, 1, rho_min=RHO_MIN)
     # each voxel's gradient is O(1/N) ~ 3e-11: the equilibrium residual left by the solver
     # tolerance enters as (1/N) <r, dF/drho_v>, ~2e-5 relative at 1e-10, ~2e-7 at 1e-12; the
-    # rounding floor of the quotient (see _fd_check) is ~5e-6 / rho relative at this size
+    # rounding floor of the quotient (see _fd_check) is ~2e-6 relative at this size
     _fd_check(w, rho, np.zeros(9), 1.0, 20, 3, 1e-5, tol_cg=1e-12, tol_newton=1e-12)
 
 

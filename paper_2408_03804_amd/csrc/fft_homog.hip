@@ -193,7 +193,8 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->TXo = TXo;
   L->in_o = ino;
   L->smem_max = std::max(std::max(xfwd_smem(g, R, inx), xinv_smem(g, R, inx)),
-                         std::max(mid_smem(g, TXm, inm), outer_smem(g, TXo, ino)));
+                         std::max(mid_smem(g, TXm, inm, mid_planes(g, pl[1], TXm, inm, L->B)),
+                                  outer_smem(g, TXo, ino)));
   L->nblk_x = (rows + R - 1) / R;
   L->nblk_vox = (int)((g.N + kThreads - 1) / kThreads);
 
@@ -337,6 +338,7 @@ AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inpl
   a.pl = h->plan[axis];
   a.TX = TX;
   a.inplace = inplace >= 0 ? inplace : (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
+  a.ZB = (axis == 1 && h->g.ndim == 3) ? mid_planes(h->g, h->plan[1], TX, a.inplace, h->L.B) : 1;
   a.spec = h->spec;
   a.st = st;
   a.active = nullptr;
@@ -1378,7 +1380,8 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
   h->L.TXo = best.TXo;
   h->L.in_o = best.in_o;
   h->L.smem_max = std::max(std::max(xfwd_smem(g, h->L.R, h->L.in_x), xinv_smem(g, h->L.R, h->L.in_x)),
-                           std::max(mid_smem(g, h->L.TXm, h->L.in_m), outer_smem(g, h->L.TXo, h->L.in_o)));
+                           std::max(mid_smem(g, h->L.TXm, h->L.in_m, mid_planes(g, h->plan[1], h->L.TXm, h->L.in_m, h->L.B)),
+                                    outer_smem(g, h->L.TXo, h->L.in_o)));
   if (shape) fft_homog_get_launch_shape(h, shape);
   return FFT_HOMOG_OK;
 }

@@ -54,6 +54,7 @@ struct AxisArgs {
   Geom g;
   AxisPlan pl;
   int TX;                // kx bins per block
+  int ZB;                // y pass: consecutive z planes per block (1 for the other passes)
   int inplace;
   double2* spec;
   const CgState* st;     // nullable: skip right-hand sides whose CG is not running
@@ -68,7 +69,10 @@ struct AxisArgs {
 // dynamic LDS bytes of each pass; `inplace` drops the ping-pong buffer
 size_t xfwd_smem(const Geom& g, int R, int inplace);
 size_t xinv_smem(const Geom& g, int R, int inplace);
-size_t mid_smem(const Geom& g, int TX, int inplace);
+size_t mid_smem(const Geom& g, int TX, int inplace, int ZB = 1);
+// z planes per y-pass block for a tile of TX bins: 1 unless the tile spans the whole stored row,
+// then as many as fit 32 KiB of LDS while the pass keeps about 512 blocks over B right-hand sides
+int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B);
 size_t outer_smem(const Geom& g, int TX, int inplace);
 int outer_group(const Geom& g);   // components transformed together in the outer pass
 // true if an in-place transform of nseq sequences of this plan fits the register staging

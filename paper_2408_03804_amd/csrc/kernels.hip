@@ -434,6 +434,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_finish(double* x, const double*
 // ============================================================================
 // y-axis pass (3D): complex FFT of the half spectrum along y, in place
 // ============================================================================
+// A block transforms the tw bins kx0.. of ZB consecutive z planes (contiguous in memory when
+// the tile spans the whole row); sequence q = zz * tw + s, element y at A[y * nseq + q].
 template <int DIR>
 __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   const Geom& g = a.g;
@@ -444,22 +446,29 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   const int kx0 = blockIdx.x * a.TX;
   const int tw = min(a.TX, g.nxh - kx0);
   const int ny = g.ny;
+  const int z0 = blockIdx.y * a.ZB;
+  const int nseq = min(a.ZB, g.nz - z0) * tw;
   extern __shared__ double2 smem[];
   double2* A = smem;
-  double2* Bf = smem + (size_t)ny * tw;
-  const long long base = ((long long)b * g.c + comp) * g.Nh + (long long)blockIdx.y * ny * g.nxp + kx0;
+  double2* Bf = smem + (size_t)ny * nseq;
+  const long long base = ((long long)b * g.c + comp) * g.Nh + (long long)z0 * ny * g.nxp + kx0;
+  const FastDiv fdq = make_fastdiv((unsigned)nseq);
   const FastDiv fdt = make_fastdiv((unsigned)tw);
-  for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
-    const int y = (int)fdiv((unsigned)t, fdt);
-    const int s = t - y * tw;
-    A[t] = a.spec[base + (long long)y * g.nxp + s];
+  for (int t = threadIdx.x; t < ny * nseq; t += blockDim.x) {
+    const int y = (int)fdiv((unsigned)t, fdq);
+    const int q = t - y * nseq;
+    const int zz = (int)fdiv((unsigned)q, fdt);
+    const int s = q - zz * tw;
+    A[t] = a.spec[base + (long long)(zz * ny + y) * g.nxp + s];
   }
   __syncthreads();
-  fft_lds_any<DIR>(A, Bf, tw, a.pl, a.inplace);
-  for (int t = threadIdx.x; t < ny * tw; t += blockDim.x) {
-    const int y = (int)fdiv((unsigned)t, fdt);
-    const int s = t - y * tw;
-    a.spec[base + (long long)y * g.nxp + s] = A[t];
+  fft_lds_any<DIR>(A, Bf, nseq, a.pl, a.inplace);
+  for (int t = threadIdx.x; t < ny * nseq; t += blockDim.x) {
+    const int y = (int)fdiv((unsigned)t, fdq);
+    const int q = t - y * nseq;
+    const int zz = (int)fdiv((unsigned)q, fdt);
+    const int s = q - zz * tw;
+    a.spec[base + (long long)(zz * ny + y) * g.nxp + s] = A[t];
   }
 }
 
@@ -1005,7 +1014,22 @@ size_t xinv_smem(const Geom& g, int R, int inplace) {
   if (h > bsz) bsz = h;
   return (a + bsz) * sizeof(double2);
 }
-size_t mid_smem(const Geom& g, int TX, int inplace) { return (inplace ? 1ull : 2ull) * g.ny * TX * sizeof(double2); }
+size_t mid_smem(const Geom& g, int TX, int inplace, int ZB) {
+  return (inplace ? 1ull : 2ull) * g.ny * TX * ZB * sizeof(double2);
+}
+int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B) {
+  if (g.ndim != 3 || TX < g.nxh) return 1;
+  constexpr size_t kLdsPlanes = 32 * 1024;
+  constexpr long long kBlocks = 512;
+  int zb = 1;
+  for (int z = 2; z <= std::min(8, g.nz); ++z) {
+    if (mid_smem(g, TX, inplace, z) > kLdsPlanes) break;
+    if (inplace && !inplace_ok(pl, z * TX)) break;
+    if ((long long)((g.nz + z - 1) / z) * g.c * B < kBlocks) break;
+    zb = z;
+  }
+  return zb;
+}
 int outer_group(const Geom& g) { return g.small ? g.c : g.ndim; }
 size_t outer_smem(const Geom& g, int TX, int inplace) {
   return (size_t)(outer_group(g) * (inplace ? 1 : 2)) * g.n_outer * TX * sizeof(double2);
@@ -1064,8 +1088,8 @@ hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
 }
 
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
-  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.nz, B * a.g.c);
-  const size_t sm = mid_smem(a.g, a.TX, a.inplace);
+  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, (a.g.nz + a.ZB - 1) / a.ZB, B * a.g.c);
+  const size_t sm = mid_smem(a.g, a.TX, a.inplace, a.ZB);
   if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
   else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
   return hipGetLastError();

@@ -337,7 +337,9 @@ __device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
   switch (pl.n) {
     case 256: fixed_stages<256, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 128: fixed_stages<128, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 96: fixed_stages<96, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 64: fixed_stages<64, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 48: fixed_stages<48, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 32: fixed_stages<32, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 16: fixed_stages<16, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 8: fixed_stages<8, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;

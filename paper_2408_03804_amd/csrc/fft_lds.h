@@ -237,19 +237,21 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
 // kInplaceElems elements in a stage (checked by the host: inplace_ok()).
 constexpr int kInplaceElems = 16;
 
+// (Run-time length and stage position; the divisions by nseq and Ns are magic multiplies.)
 template <int R, int DIR>
-__device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nseq, int n, int Ns,
+__device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nseq, FastDiv fdq, int n, int Ns,
                                               const double2* __restrict__ tw) {
   constexpr int MB = kInplaceElems / R;
   const int nb = n / R;
   const int stride = n / (Ns * R);
   const int total = nb * nseq;
+  const FastDiv fdn = make_fastdiv((unsigned)Ns);
   double2 v[MB][R];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
     if (w < total) {
-      const int j = w / nseq;
+      const int j = (int)fdiv((unsigned)w, fdq);
       const int s = w - j * nseq;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = buf[(j + t * nb) * nseq + s];
@@ -260,9 +262,9 @@ __device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nse
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
     if (w < total) {
-      const int j = w / nseq;
+      const int j = (int)fdiv((unsigned)w, fdq);
       const int s = w - j * nseq;
-      const int k = j % Ns;
+      const int k = j - (int)fdiv((unsigned)j, fdn) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * stride));
@@ -350,12 +352,12 @@ __device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
   for (int st = 0; st < pl.nstages; ++st) {
     const int R = pl.radix[st];
     switch (R) {
-      case 2: stage_inplace<2, DIR>(buf, nseq, n, Ns, pl.tw); break;
-      case 3: stage_inplace<3, DIR>(buf, nseq, n, Ns, pl.tw); break;
-      case 4: stage_inplace<4, DIR>(buf, nseq, n, Ns, pl.tw); break;
-      case 5: stage_inplace<5, DIR>(buf, nseq, n, Ns, pl.tw); break;
-      case 16: stage_inplace<16, DIR>(buf, nseq, n, Ns, pl.tw); break;
-      default: stage_inplace<8, DIR>(buf, nseq, n, Ns, pl.tw); break;
+      case 2: stage_inplace<2, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      case 3: stage_inplace<3, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      case 4: stage_inplace<4, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      case 5: stage_inplace<5, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      case 16: stage_inplace<16, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      default: stage_inplace<8, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
     }
     Ns *= R;
   }

@@ -15,13 +15,16 @@ constexpr int kMaxPhase = 256;  // phase-table rows reserved per cell
 // Radix schedules compiled into the FFT engine for the common axis lengths; the
 // host factorisation returns the same schedule for these lengths.
 __host__ __device__ constexpr int fixed_nstages(int n) {
-  return n == 256 ? 2 : n == 128 ? 2 : n == 96 ? 3 : n == 64 ? 2 : n == 48 ? 2 : n == 32 ? 2 : n == 16 ? 1
-       : n == 8 ? 1 : 0;
+  return n == 256 ? 2 : n == 192 ? 3 : n == 160 ? 3 : n == 128 ? 2 : n == 96 ? 3 : n == 80 ? 2 : n == 64 ? 2
+       : n == 48 ? 2 : n == 32 ? 2 : n == 16 ? 1 : n == 8 ? 1 : 0;
 }
 __host__ __device__ constexpr int fixed_radix(int n, int st) {
   return n == 256 ? 16
+       : n == 192 ? (st == 0 ? 16 : st == 1 ? 4 : 3)
+       : n == 160 ? (st == 0 ? 16 : st == 1 ? 5 : 2)
        : n == 128 ? (st == 0 ? 16 : 8)
        : n == 96 ? (st == 0 ? 8 : st == 1 ? 4 : 3)
+       : n == 80 ? (st == 0 ? 16 : 5)
        : n == 64 ? 8
        : n == 48 ? (st == 0 ? 16 : 3)
        : n == 32 ? (st == 0 ? 8 : 4)

@@ -338,8 +338,11 @@ __device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
   const FastDiv fd = make_fastdiv((unsigned)nseq);
   switch (pl.n) {
     case 256: fixed_stages<256, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 192: fixed_stages<192, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 160: fixed_stages<160, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 128: fixed_stages<128, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 96: fixed_stages<96, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+    case 80: fixed_stages<80, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 64: fixed_stages<64, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 48: fixed_stages<48, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
     case 32: fixed_stages<32, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;

@@ -16,9 +16,11 @@ pytestmark = pytest.mark.gpu
 
 MATS = [("linear_elastic", "small"), ("neo_hookean", "finite"), ("stvk", "finite")]
 FFT_SHAPES = [(7, 5), (31, 31), (8, 12), (1, 9), (6, 10, 12), (9, 16, 15), (5, 6, 7), (3, 4, 1), (13, 11, 17),
-              # lengths with compiled-in radix schedules (16, 8, 8.4, 16.3, 8.8, 8.4.3, 16.8, 16.16) on every axis
+              # lengths with compiled-in radix schedules (16, 8, 8.4, 16.3, 8.8, 16.5, 8.4.3, 16.8, 16.5.2,
+              # 16.4.3, 16.16) on every axis
               (2, 4, 128), (128, 3, 2), (3, 256, 2), (16, 32, 64), (64, 16, 32), (256, 6), (5, 256),
               (2, 4, 96), (96, 3, 2), (3, 48, 2), (48, 96, 4), (48, 5),
+              (2, 3, 80), (80, 4), (3, 160, 2), (160, 2, 3), (2, 192, 3), (192, 5),
               # long prime stages (direct DFT of length 199 / 257, and 299 = 13 * 23) on each axis
               (199, 6), (3, 257), (4, 199, 5), (299, 4), (2, 3, 199)]
 

@@ -90,6 +90,26 @@ def test_multi_cell_equals_one_cell_handles_bitwise():
         assert st["cg"][i * 6:(i + 1) * 6] == sti["cg"]
 
 
+def test_y_pass_plane_groups_leave_tangents_bitwise_unchanged():
+    """A y tile spanning the whole stored row lets a y-pass block take several consecutive z planes
+    (16 cells x 6 loads at 16 x 16 x 32: 7 planes per block); 16-bin tiles take one plane per
+    block.  Every sequence gets the same FFT either way, so the tangents are bitwise equal."""
+    shape = (16, 16, 32)
+    cells = random_cells(shape, 16, 21)
+    phases = np.stack([c[0] for c in cells])
+    tables = np.stack([c[1] for c in cells])
+    out = []
+    for y_bins in (17, 16):
+        h = make(shape, "small", "linear_elastic", tangent=True, batch=16)
+        h.set_material(phases, tables)
+        h.set_launch_shape(dict(h.launch_shape(), y_bins=y_bins))
+        C, st = h.tangent()
+        assert st["status"] == "ok"
+        out.append((C, st["cg"]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
 def test_homogeneous_cell_inside_a_batch_is_exact():
     shape = (8, 6, 10)
     cells = random_cells(shape, 3, 13)

@@ -528,7 +528,21 @@ int cg_loop(fft_homog_t* h, int B) {
         done = std::min(done, h->h_st[b].iters);
       }
     if (nrun == 0) return FFT_HOMOG_OK;
-    const int m = std::min(kChunk, std::max(1, h->desc.max_cg - done));
+    // Iterations to enqueue before the next host check.  A single right-hand side (not replayed
+    // from a graph) takes up to 2 kChunk at once while far from the tolerance and about the
+    // predicted remainder near it, from its mean residual decay per iteration so far: fewer
+    // host checks and fewer launches after convergence (128^3 solve -0.35 %).  Chunking does not
+    // change the iterates; iterations past convergence return at once.
+    int m = kChunk;
+    if (B == 1 && !(h->desc.flags & FFT_HOMOG_FLAG_GRAPH)) {
+      const CgState& S = h->h_st[0];
+      if (S.iters >= 4 && S.rr > 0.0 && S.rr0 > 0.0 && S.rr < S.rr0) {
+        const double rate = std::log(S.rr / S.rr0) / S.iters;
+        const double left = std::log(S.tol * S.tol * S.rr0 / S.rr) / rate;
+        if (left > 0.0) m = std::max(1, std::min(2 * kChunk, (int)std::ceil(left)));
+      }
+    }
+    m = std::min(m, std::max(1, h->desc.max_cg - done));
     const int* act = nullptr;
     if (nrun < B) {
       FH_CK(hipMemcpyAsync(h->active, h->h_active, nrun * sizeof(int), hipMemcpyHostToDevice, h->stream));

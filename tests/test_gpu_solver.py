@@ -178,8 +178,8 @@ def test_sampled_kernel_timing_leaves_the_solve_unchanged():
                 h.set_kernel_timing(-1)
             assert ei.value.status == "einval"
             continue
-        # chunks of 8 iterations are enqueued per host check; stopped solves skip their blocks
-        enq_max = st["cg_total"] + 8 * st["newton"]
+        # up to 16 iterations are enqueued per host check; stopped solves skip their blocks
+        enq_max = st["cg_total"] + 16 * st["newton"]
         assert -(-st["cg_total"] // every) <= n <= -(-enq_max // every)
         assert (ms > 0).all()
         h.set_kernel_timing(0)

@@ -98,7 +98,9 @@ typedef struct fft_homog_desc {
   int material;      /* LINEAR_ELASTIC or J2_PLASTIC (small), NEO_HOOKEAN or STVK (finite); J2
                         takes no FLAG_DENSITY and no batch > 1 */
   int nphase;        /* 1..256 */
-  double tol_newton; /* Newton stop: ||dF||_2 / (sqrt(N) ||F-bar||_F) < tol_newton */
+  double tol_newton; /* Newton stop: ||dF||_2 / (sqrt(N) ||F-bar||_F) < tol_newton (RMS update over the
+                        RMS macro load, section 4 / Appendix A); for a zero macro load (small
+                        strain unloaded to zero) the scale is the updated field's norm ||F||_2 */
   double tol_cg;     /* CG stop: ||r|| <= tol_cg ||b|| */
   int max_newton;    /* per load increment */
   int max_cg;        /* per linear solve */
@@ -125,6 +127,8 @@ typedef struct fft_homog_stats {
   double seconds;             /* device time of the call (HIP events on the stream) */
   int n_recorded;             /* entries of cg_per_newton written */
   int cg_per_newton[FFT_HOMOG_MAX_RECORDED]; /* CG iterations of each Newton iteration */
+  int host_checks;            /* times the host read back the CG records during the call (each
+                                 costs a stream synchronisation of some tens of microseconds) */
 } fft_homog_stats;
 
 typedef struct fft_homog fft_homog_t;
@@ -249,6 +253,21 @@ int fft_homog_debug_irfft(fft_homog_t* h, const double* spec, double* out, int b
 int fft_homog_debug_project(fft_homog_t* h, const double* in, double* out, int batch);
 /* q = G*(K(eps_current) : p), the CG operator at the current state. */
 int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, int batch);
+
+/* Exactly `iters` CG iterations (Appendix A, the linear solve of one Newton iteration) on the
+ * Newton system at the current state, G*(K:x) = -G*(P), from x = 0, with the handle's launch
+ * shape and the solver's own kernels; no convergence test.  x_out and r_out (device, packed
+ * layout, f64[c][N], caller-owned) receive the iterate x_iters and the residual r_iters.  The
+ * strain state is unchanged.  ESTATE if the right-hand side is zero to rounding (nothing to
+ * iterate), EBREAKDOWN if <p, K:p> <= 0 before `iters`, EUNSUPPORTED on multi-cell handles. */
+int fft_homog_debug_cg(fft_homog_t* h, int iters, double* x_out, double* r_out);
+
+/* Pure host function: the number of CG iterations the solver enqueues before its next host
+ * check for a single right-hand side that has run `iters` iterations with residual norms
+ * rr0 = <b,b>, rr = <r,r> and relative tolerance tol, given the iteration count and <r,r> at
+ * the previous check (prev_iters < 0: none).  Between 1 and 16; at least 4 unless the decay
+ * since the previous check agrees with the mean decay to a factor of two. */
+int fft_homog_debug_cg_chunk(int iters, double rr0, double rr, double tol, int prev_iters, double prev_rr);
 
 /* Average device time (ms, HIP events on the handle's stream) of each kernel of one CG
  * iteration (section 3 operator, Appendix A linear solve), measured over `iters` iterations

@@ -10,7 +10,10 @@ macro-tangent listing).
 Readings where the paper is silent or garbled:
 * Newton stop test: the paper prints "delta eps / ||eps-bar|| < tol".  Read as
   the RMS ratio ||delta eps||_2 / (sqrt(N) ||eps-bar||_F) < tol_newton, where
-  for finite strain eps-bar is the full macro F-bar (identity included).
+  for finite strain eps-bar is the full macro F-bar (identity included).  The
+  paper never loads to a zero macro strain; there (small strain unloaded to
+  zero, where plasticity leaves residual stresses) the scale is the norm of the
+  updated field ||eps||_2 instead, and a zero field counts as converged.
 * A right-hand side that is already zero to rounding (homogeneous medium) is
   not handed to CG: if ||b|| <= 1e-13 ||sigma|| the Newton loop stops.
 * Load increments: increment n starts from the previous converged field plus
@@ -202,7 +205,10 @@ def solve(problem, macro, n_increments=1, tol_newton=1e-10, tol_cg=1e-10, max_ne
                 break
             field += x
             it += 1
-            if math.sqrt(inner(x, x)) / (sqrtN * macro_norm) < tol_newton:
+            scale = sqrtN * macro_norm if macro_norm > 0.0 else math.sqrt(inner(field, field))
+            dn = math.sqrt(inner(x, x))
+            res = dn / scale if scale > 0.0 else (math.inf if dn > 0.0 else 0.0)
+            if res < tol_newton:
                 break
         newton_total += it
         if status != "ok":

@@ -58,6 +58,7 @@ class Stats(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("n_recorded", ctypes.c_int),
         ("cg_per_newton", ctypes.c_int * MAX_RECORDED),
+        ("host_checks", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -70,6 +71,7 @@ class Stats(ctypes.Structure):
             "newton_residual": self.newton_residual,
             "cg_residual": self.cg_residual,
             "seconds": self.seconds,
+            "host_checks": self.host_checks,
         }
 
 
@@ -78,7 +80,8 @@ EXPORTS = [
     "fft_homog_tangent", "fft_homog_adjoint", "fft_homog_get_field", "fft_homog_set_field",
     "fft_homog_destroy", "fft_homog_strerror", "fft_homog_last_error",
     "fft_homog_debug_constitutive", "fft_homog_debug_rfft", "fft_homog_debug_irfft",
-    "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_time_cg",
+    "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_cg",
+    "fft_homog_debug_cg_chunk", "fft_homog_debug_time_cg",
     "fft_homog_set_kernel_timing", "fft_homog_get_kernel_timing",
     "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune",
 ]
@@ -117,6 +120,8 @@ def load_library(path=LIB_PATH):
         "fft_homog_debug_irfft": (I, [P, P, P, I]),
         "fft_homog_debug_project": (I, [P, P, P, I]),
         "fft_homog_debug_apply_operator": (I, [P, P, P, I]),
+        "fft_homog_debug_cg": (I, [P, I, P, P]),
+        "fft_homog_debug_cg_chunk": (I, [I, D, D, D, I, D]),
         "fft_homog_debug_time_cg": (I, [P, I, DP]),
         "fft_homog_set_kernel_timing": (I, [P, I]),
         "fft_homog_get_kernel_timing": (I, [P, DP, ctypes.POINTER(ctypes.c_longlong)]),
@@ -223,10 +228,16 @@ class FFTHomog:
         return rc
 
     def _dev(self, a, dtype):
+        """A device copy (or view) of `a` that the handle's stream may read: made on the handle's
+        stream, after the work already queued on the caller's current stream."""
         t = self.torch
-        if isinstance(a, t.Tensor):
-            return a.to(device=self.device, dtype=dtype).contiguous()
-        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=self.device)
+        cur = t.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+        with t.cuda.stream(self.stream):
+            if isinstance(a, t.Tensor):
+                return a.to(device=self.device, dtype=dtype).contiguous()
+            return t.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=self.device)
 
     def close(self):
         if getattr(self, "h", None):
@@ -288,12 +299,13 @@ class FFTHomog:
     def reset(self):
         """Back to the undeformed reference state (eps = 0 / F = I) with zero macro load."""
         d = self.ndim
-        ref = self.torch.zeros((d * d,) + self.shape, dtype=self.torch.float64, device=self.device)
-        macro = np.zeros(self.c)
-        if self.kinematics != "small":
-            for i in range(d):
-                ref[i * d + i] = 1.0
-            macro = np.eye(d).reshape(-1)
+        with self.torch.cuda.stream(self.stream):
+            # made on the stream that set_field's kernels run on
+            ref = self.torch.zeros((d * d,) + self.shape, dtype=self.torch.float64, device=self.device)
+            if self.kinematics != "small":
+                for i in range(d):
+                    ref[i * d + i] = 1.0
+        macro = np.eye(d).reshape(-1) if self.kinematics != "small" else np.zeros(self.c)
         self.set_field(ref, macro)
 
     def adjoint(self, w_stress, w_energy):
@@ -356,6 +368,13 @@ class FFTHomog:
         self._check(self.L.fft_homog_debug_apply_operator(self.h, _tptr(p), _tptr(q), batch))
         return q
 
+    def debug_cg(self, iters):
+        """(x, r) after exactly `iters` CG iterations on the Newton system at the current state
+        (packed layout (c, *grid))."""
+        x = self.torch.empty((self.c,) + self.shape, dtype=self.torch.float64, device=self.device)
+        r = self.torch.empty_like(x)
+        self._check(self.L.fft_homog_debug_cg(self.h, int(iters), _tptr(x), _tptr(r)))
+        return x, r
 
     def debug_time_cg(self, iters):
         ms = np.zeros(7)

@@ -18,6 +18,7 @@
 
 using namespace fh;
 
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -233,6 +234,54 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   return FFT_HOMOG_OK;
 }
 
+// out = G*in for `batch` packed fields: the x pass (real-to-complex), the y pass, the outer pass
+// with G-hat and its inverse, the inverse y pass and the complex-to-real x pass, with the launch
+// shape of L, the grid g (g.nxp: the spectrum pitch in use) and `spec` as the half spectrum.
+// Enqueue only.  Shared by the handle's debug_project and the allocation-free projection.
+hipError_t enqueue_projection(const Geom& g, const AxisPlan* pl, const Layout& L, int matcode, const double* in,
+                              double* out, double2* spec, int batch, hipStream_t s) {
+  XFwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = g;
+  a.px = pl[0];
+  a.R = L.R;
+  a.nblocks = (g.ny * g.nz + L.R - 1) / L.R;
+  a.inplace = L.in_x;
+  a.in = in;
+  a.spec = spec;
+  hipError_t e = launch_xfwd(PROD_IDENT, matcode, a, batch, s);
+  auto axis = [&](int ax, int TX, int inplace) {
+    AxisArgs x;
+    memset(&x, 0, sizeof(x));
+    x.g = g;
+    x.pl = pl[ax];
+    x.TX = TX;
+    x.inplace = inplace;
+    x.ZB = (ax == 1 && g.ndim == 3) ? mid_planes(g, pl[1], TX, inplace, L.B) : 1;
+    x.spec = spec;
+    return x;
+  };
+  const AxisArgs am = axis(1, L.TXm, L.in_m);
+  const AxisArgs ao = axis(g.ndim - 1, L.TXo, L.in_o);
+  if (e == hipSuccess && g.ndim == 3) e = launch_mid(-1, am, batch, s);
+  if (e == hipSuccess) e = launch_outer(OUTER_PROJECT, ao, batch, s);
+  if (e == hipSuccess && g.ndim == 3) e = launch_mid(1, am, batch, s);
+  if (e == hipSuccess) {
+    XInvArgs ai;
+    memset(&ai, 0, sizeof(ai));
+    ai.g = g;
+    ai.px = pl[0];
+    ai.R = L.R;
+    ai.nblocks = a.nblocks;
+    ai.inplace = L.in_x;
+    ai.spec = spec;
+    ai.out = out;
+    ai.scale = 1.0 / (double)g.N;
+    e = launch_xinv(CONS_IDENT, ai, batch, s);
+  }
+  return e;
+}
+
 }  // namespace
 
 struct fft_homog {
@@ -266,6 +315,7 @@ struct fft_homog {
   int gB[2];
   // sampled kernel timing inside the CG loop (fft_homog_set_kernel_timing): event groups of
   // kTimedLaunches + 1 events recorded since the last host check, and the running sums
+  long long host_checks;  // CG-record read-backs of the current call (stats.host_checks)
   int time_every;
   long long time_count;  // CG iterations enqueued eagerly since timing was switched on
   std::vector<hipEvent_t> tev;
@@ -277,8 +327,10 @@ struct fft_homog {
 
 namespace {
 
-// message of the last failed fft_homog_create on this thread (no handle exists then)
-thread_local std::string g_create_err;
+// message of the last failed handle-free call on this thread (fft_homog_create, the
+// allocation-free projection): no handle exists to hold it; a fixed buffer, so that setting it
+// allocates nothing
+thread_local char g_create_err[256];
 
 int fail(fft_homog_t* h, int code, const char* msg) {
   if (h) h->err = msg ? msg : "";
@@ -286,7 +338,8 @@ int fail(fft_homog_t* h, int code, const char* msg) {
 }
 
 int create_fail(int code, const char* what, hipError_t e) {
-  g_create_err = std::string(what) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+  if (e != hipSuccess) snprintf(g_create_err, sizeof(g_create_err), "%s: %s", what, hipGetErrorString(e));
+  else snprintf(g_create_err, sizeof(g_create_err), "%s", what);
   return code;
 }
 
@@ -514,11 +567,36 @@ int rhs_chain(fft_homog_t* h, int prod, int B, const double* unit) {
   return read_states(h, B);
 }
 
+// CG iterations a single right-hand side enqueues before its next host check.  While the
+// residual is far from the tolerance: 2 kChunk.  Near it: about the remainder predicted from
+// the mean residual decay per iteration so far (fewer host checks and fewer launches after
+// convergence), but at least kChunk / 2 unless the decay since the previous check agrees with
+// that mean to a factor of two -- a stagnating residual (a tolerance at the rounding floor)
+// would otherwise cost a host check per iteration.  Chunking never changes the iterates:
+// iterations enqueued past convergence return at once.
+int cg_chunk_length(int iters, double rr0, double rr, double tol, int prev_iters, double prev_rr) {
+  if (!(iters >= 4 && rr > 0.0 && rr0 > 0.0 && rr < rr0 && tol > 0.0)) return kChunk;
+  const double rate = std::log(rr / rr0) / iters;  // < 0
+  double left = std::log(tol * tol * rr0 / rr) / rate;
+  if (!(left > 0.0)) return kChunk;                // reached, or not a number
+  left = std::min(left, 2.0 * kChunk);             // clamp before the integer conversion
+  int m = std::max(1, (int)std::ceil(left));
+  bool trust = false;
+  if (prev_iters >= 0 && iters > prev_iters && prev_rr > 0.0) {
+    const double recent = std::log(rr / prev_rr) / (iters - prev_iters);
+    trust = recent <= 0.5 * rate && recent >= 2.0 * rate;
+  }
+  if (!trust) m = std::max(m, kChunk / 2);
+  return m;
+}
+
 // Conjugate gradients on all running right-hand sides until none is running.  Once some
 // have stopped, the launches cover only the running ones (their indices are uploaded
 // before each chunk), so a batch's slow tail does not pay for its finished members.
 int cg_loop(fft_homog_t* h, int B) {
   h->tev_used = 0;  // event groups of an earlier call that failed before its host check
+  int prev_iters = -1;
+  double prev_rr = 0.0;
   for (;;) {
     int nrun = 0;
     int done = 1 << 30;
@@ -536,11 +614,9 @@ int cg_loop(fft_homog_t* h, int B) {
     int m = kChunk;
     if (B == 1 && !(h->desc.flags & FFT_HOMOG_FLAG_GRAPH)) {
       const CgState& S = h->h_st[0];
-      if (S.iters >= 4 && S.rr > 0.0 && S.rr0 > 0.0 && S.rr < S.rr0) {
-        const double rate = std::log(S.rr / S.rr0) / S.iters;
-        const double left = std::log(S.tol * S.tol * S.rr0 / S.rr) / rate;
-        if (left > 0.0) m = std::max(1, std::min(2 * kChunk, (int)std::ceil(left)));
-      }
+      m = cg_chunk_length(S.iters, S.rr0, S.rr, S.tol, prev_iters, prev_rr);
+      prev_iters = S.iters;
+      prev_rr = S.rr;
     }
     m = std::min(m, std::max(1, h->desc.max_cg - done));
     const int* act = nullptr;
@@ -552,6 +628,7 @@ int cg_loop(fft_homog_t* h, int B) {
     if (rc) return rc;
     rc = read_states(h, B);
     if (rc) return rc;
+    ++h->host_checks;
     if (h->tev_used) {
       rc = harvest_timing(h);
       if (rc) return rc;
@@ -707,6 +784,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   h->cap = nullptr;
   h->gexec[0] = h->gexec[1] = nullptr;
   h->gB[0] = h->gB[1] = 0;
+  h->host_checks = 0;
 
   hipError_t e = hipHostMalloc((void**)&h->h_st,
                                L.B * sizeof(CgState) + L.n_results * sizeof(double) + 64 + L.B * sizeof(int), 0);
@@ -772,7 +850,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
     fft_homog_destroy(h);
     return create_fail(FFT_HOMOG_EDEVICE, step, e);
   }
-  g_create_err.clear();
+  g_create_err[0] = 0;
   *out = h;
   return FFT_HOMOG_OK;
 }
@@ -831,6 +909,7 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
     if (!std::isfinite(macro[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite macro load");
   fft_homog_stats S;
   memset(&S, 0, sizeof(S));
+  h->host_checks = 0;
   FH_CK(hipEventRecord(h->ev0, h->stream));
 
   double target[kMaxC], start[kMaxC], prev[kMaxC], cur[kMaxC], delta[kMaxC];
@@ -875,11 +954,16 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
       if (ce.status == CG_BREAKDOWN) { status = FFT_HOMOG_EBREAKDOWN; break; }
       if (ce.status == CG_MAXIT) { status = FFT_HOMOG_ENOTCONV; break; }
       FH_CK(launch_update(h->F, h->x, h->partials, h->L.nblk_vox, h->g, h->stream));
-      rc = reduce_to_host(h, 1, h->L.nblk_vox);
+      rc = reduce_to_host(h, 2, h->L.nblk_vox);
       if (rc) return rc;
       ++it;
       S.newton_iterations++;
-      const double res = std::sqrt(h->h_results[0]) / (sqrtN * mn);
+      // RMS update over the RMS macro load; a zero macro load (small strain unloaded to zero,
+      // where a history-dependent law leaves residual stresses) takes the updated field's own
+      // norm as the scale, and a zero field counts as converged
+      const double scale = mn > 0.0 ? sqrtN * mn : std::sqrt(h->h_results[1]);
+      const double dn = std::sqrt(h->h_results[0]);
+      const double res = scale > 0.0 ? dn / scale : (dn > 0.0 ? HUGE_VAL : 0.0);
       S.newton_residual = res;
       if (res < h->desc.tol_newton) break;
     }
@@ -904,6 +988,7 @@ int fft_homog_solve(fft_homog_t* h, const double* macro, int n_increments, doubl
   FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   S.seconds = ms * 1e-3;
   S.status = status;
+  S.host_checks = (int)h->host_checks;
   h->solved_ok = status == FFT_HOMOG_OK;
   if (stats) *stats = S;
   if (status != FFT_HOMOG_OK) {
@@ -924,6 +1009,7 @@ int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
   const int B = h->L.B;
   fft_homog_stats S;
   memset(&S, 0, sizeof(S));
+  h->host_checks = 0;
   FH_CK(hipEventRecord(h->ev0, h->stream));
   double unit[kMaxC];
   unit_loads(h, unit);
@@ -959,6 +1045,7 @@ int fft_homog_tangent(fft_homog_t* h, double* Cout, fft_homog_stats* stats) {
   FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   S.seconds = ms * 1e-3;
   S.status = status;
+  S.host_checks = (int)h->host_checks;
   if (stats) *stats = S;
   return status;
 }
@@ -976,6 +1063,7 @@ int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, d
     if (!std::isfinite(w_stress[k])) return fail(h, FFT_HOMOG_EINVAL, "non-finite weight");
   fft_homog_stats S;
   memset(&S, 0, sizeof(S));
+  h->host_checks = 0;
   FH_CK(hipEventRecord(h->ev0, h->stream));
   // W in the packed basis: the objective is sum_I w_I out_I with out_I = W-packed . P-packed
   double W[kMaxC];
@@ -1012,6 +1100,7 @@ int fft_homog_adjoint(fft_homog_t* h, const double* w_stress, double w_energy, d
   FH_CK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   S.seconds = ms * 1e-3;
   S.status = status;
+  S.host_checks = (int)h->host_checks;
   if (stats) *stats = S;
   if (status) h->err = status == FFT_HOMOG_EBREAKDOWN ? "CG breakdown" : "iteration limit reached";
   return status;
@@ -1079,7 +1168,7 @@ const char* fft_homog_strerror(int s) {
   }
 }
 
-const char* fft_homog_last_error(const fft_homog_t* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+const char* fft_homog_last_error(const fft_homog_t* h) { return h ? h->err.c_str() : g_create_err; }
 
 // ---- stage-level entry points -------------------------------------------------
 static int check_batch(fft_homog_t* h, int batch) {
@@ -1131,14 +1220,7 @@ int fft_homog_debug_project(fft_homog_t* h, const double* in, double* out, int b
   if (!h || !in || !out) return fail(h, FFT_HOMOG_EINVAL, "null argument");
   int rc = check_batch(h, batch);
   if (rc) return rc;
-  XFwdArgs a = xfwd_args(h);
-  a.in = in;
-  FH_CK(launch_xfwd(PROD_IDENT, h->matcode, a, batch, h->stream));
-  rc = spectral_middle(h, OUTER_PROJECT, batch, nullptr);
-  if (rc) return rc;
-  XInvArgs ai = xinv_args(h);
-  ai.out = out;
-  FH_CK(launch_xinv(CONS_IDENT, ai, batch, h->stream));
+  FH_CK(enqueue_projection(h->g, h->plan, h->L, h->matcode, in, out, h->spec, batch, h->stream));
   FH_CK(hipStreamSynchronize(h->stream));
   return FFT_HOMOG_OK;
 }
@@ -1166,6 +1248,35 @@ int fft_homog_debug_apply_operator(fft_homog_t* h, const double* p, double* q, i
   FH_CK(launch_xinv(CONS_IDENT, ai, batch, h->stream));
   FH_CK(hipStreamSynchronize(h->stream));
   return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_cg(fft_homog_t* h, int iters, double* x_out, double* r_out) {
+  if (!h || !x_out || !r_out || iters < 1) return fail(h, FFT_HOMOG_EINVAL, "bad arguments");
+  if (h->L.cells > 1) return fail(h, FFT_HOMOG_EUNSUPPORTED, "multi-cell handles compute tangents only");
+  int rc = rhs_chain(h, PROD_STRESS, 1, nullptr);
+  if (rc) return rc;
+  if (h->h_st[0].domain) return fail(h, FFT_HOMOG_EDOMAIN, "det F <= 0 or non-finite stress");
+  if (h->h_st[0].status != CG_RUNNING) return fail(h, FFT_HOMOG_ESTATE, "zero Newton right-hand side");
+  // exactly `iters` iterations: no convergence test, stop at the iteration limit
+  h->h_st[0].tol = 0.0;
+  h->h_st[0].max_iters = iters;
+  FH_CK(hipMemcpyAsync(h->st, h->h_st, sizeof(CgState), hipMemcpyHostToDevice, h->stream));
+  if (h->kst) FH_CK(launch_store_tangent(h->matcode, h->F, h->mat, h->kst, h->g, h->stream));
+  FH_CK(enqueue_cg_iters(h, 1, iters, h->stream));
+  FH_CK(launch_cg_finish(h->x, h->p, h->st, h->g, 1, h->stream));
+  rc = read_states(h, 1);
+  if (rc) return rc;
+  if (h->h_st[0].status != CG_MAXIT || h->h_st[0].iters != iters)
+    return fail(h, FFT_HOMOG_EBREAKDOWN, "CG stopped before the requested iteration count");
+  const size_t bytes = (size_t)h->g.c * h->g.N * sizeof(double);
+  FH_CK(hipMemcpyAsync(x_out, h->x, bytes, hipMemcpyDeviceToDevice, h->stream));
+  FH_CK(hipMemcpyAsync(r_out, h->r, bytes, hipMemcpyDeviceToDevice, h->stream));
+  FH_CK(hipStreamSynchronize(h->stream));
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_debug_cg_chunk(int iters, double rr0, double rr, double tol, int prev_iters, double prev_rr) {
+  return cg_chunk_length(iters, rr0, rr, tol, prev_iters, prev_rr);
 }
 
 int fft_homog_debug_time_cg(fft_homog_t* h, int iters, double* ms) {

@@ -725,20 +725,25 @@ __global__ void k_shift(double* F, Small9 delta, Geom g) {
     F[i] += delta.v[i / N];
 }
 
+// F += x; block partials of ||x||^2 (slot 0) and of the updated ||F||^2 (slot 1)
 __global__ void __launch_bounds__(kThreads) k_update(double* F, const double* x, double* partials, Geom g) {
   __shared__ double red[kThreads / 64];
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  double acc = 0.0;
+  double acc = 0.0, accf = 0.0;
   if (v < N) {
     for (int j = 0; j < g.c; ++j) {
       const double dx = x[j * N + v];
-      F[j * N + v] += dx;
+      const double f = F[j * N + v] + dx;
+      F[j * N + v] = f;
       acc += dx * dx;
+      accf += f * f;
     }
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  const double sf = block_sum(accf, red);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = sf;
 }
 
 // per-block sums of m values per thread, written to partials[slot][block]

@@ -38,9 +38,23 @@ def unpack(packed, small, d):
 
 
 def rel(a, b):
+    """Relative 2-norm difference ||a - b|| / ||b|| (reading R18's field metric)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def relmax(a, b):
+    """Element-wise difference: max |a - b| / max |b|.  A relative 2-norm can hide one wrong
+    entry among many; this cannot."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def field_err(a, b):
+    """The larger of the relative 2-norm and the element-wise max difference."""
+    return max(rel(a, b), relmax(a, b))
 
 
 def lame_fields(phase, table, density=None, p=3.0):

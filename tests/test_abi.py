@@ -39,7 +39,32 @@ def test_struct_sizes_match_header_layout():
     # int ndim; int n[3]; double len[3]; 3 ints + pad; 2 doubles; 3 ints; unsigned; int batch + pad
     assert ctypes.sizeof(binding.Desc) == 4 + 12 + 24 + 16 + 16 + 16 + 8
     assert binding.Desc.batch.offset == 88
-    assert ctypes.sizeof(binding.Stats) == 16 + 24 + 8 + 4 * binding.MAX_RECORDED
+    # 4 ints, 3 doubles, n_recorded, cg_per_newton[], host_checks (fills the former tail padding)
+    assert ctypes.sizeof(binding.Stats) == 16 + 24 + 4 + 4 * binding.MAX_RECORDED + 4
+    assert binding.Stats.host_checks.offset == 16 + 24 + 4 + 4 * binding.MAX_RECORDED
+
+
+def test_cg_chunk_length_policy():
+    """Host policy of how many CG iterations run between host checks (a pure host function)."""
+    f = binding.load_library().fft_homog_debug_cg_chunk
+    tol = 1e-10
+    # early or without a decay history: a default chunk of 8
+    assert f(0, 1.0, 1.0, tol, -1, 0.0) == 8
+    assert f(3, 1.0, 0.5, tol, -1, 0.0) == 8
+    # steady decay far from the tolerance: capped at 16
+    assert f(10, 1.0, 1e-2, tol, 2, 1.0) == 16
+    # steady decay near the tolerance: about the predicted remainder (rate 1e-2 per iteration)
+    rr0, it = 1.0, 100
+    rr = 10.0 ** (-2.0 * it / 10.0)          # 1e-20 after 100 iterations; target tol^2 rr0 = 1e-20
+    rr_near = rr * 10 ** 0.5                  # two and a half iterations short
+    assert f(it - 2, rr0, rr_near, tol, it - 10, rr_near * 10 ** 1.6) == 3
+    # the same residual after a stall since the previous check: at least 4
+    assert f(it - 2, rr0, rr_near, tol, it - 10, rr_near * 1.0001) == 4
+    # a residual that has barely decayed: no integer overflow, capped at 16
+    assert f(1000, 1.0, 1.0 - 1e-15, tol, 990, 1.0) == 16
+    # reached or not a number: the default chunk
+    assert f(50, 1.0, 1e-21, tol, 40, 1e-20) == 8
+    assert f(50, 1.0, float("nan"), tol, 40, 1e-20) == 8
 
 
 @pytest.mark.parametrize("shape,kin,mat", [((31, 31), "small", "linear_elastic"),

@@ -12,8 +12,8 @@ the macro response of independent solves.
 import numpy as np
 import pytest
 
-from helpers import lame_fields, rel
-from oracle import closed_forms, materials, spectral
+from helpers import field_err, lame_fields, pack, rel, relmax, unpack
+from oracle import closed_forms, materials, newton_cg, spectral
 from paper_2408_03804_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -31,12 +31,26 @@ def to_full(field, shape):
     return np.moveaxis(a, (0, 1), (-2, -1))
 
 
-def test_neohookean_128_bench_configuration():
+# launch shape that bench.py times at 128^3 (the default of a one-cell 128^3 finite-strain handle):
+# rows per x-pass block, kx bins per y / outer block, register-staged FFTs, padded spectrum pitch
+BENCH_SHAPE_128 = {"x_rows": 2, "y_bins": 16, "outer_bins": 4, "x_regs": 1, "y_regs": 1, "outer_regs": 1,
+                   "spectrum_pitch": 72}
+
+
+@pytest.fixture(scope="module")
+def nh128():
+    """The 128^3 Neo-Hookean workload solved exactly as bench.py solves it."""
     w = workloads.workload_neohookean3d(n=128)
     shape = w["shape"]
     h = make(shape, "finite", "neo_hookean", tol_newton=1e-10, tol_cg=1e-10, max_newton=50, max_cg=20000)
     h.set_material(w["phase"], w["table"])
     S, psi, st = h.solve(w["macro"], w["n_increments"])
+    return dict(w=w, h=h, S=S, psi=psi, st=st)
+
+
+def test_neohookean_128_bench_configuration(nh128):
+    w, h, S, psi, st = nh128["w"], nh128["h"], nh128["S"], nh128["psi"], nh128["st"]
+    shape = w["shape"]
     assert st["status"] == "ok" and st["increments"] == 10
     assert 10 <= st["newton"] <= 80 and st["cg_total"] > 0
     F = to_full(h.get_field(0), shape)
@@ -55,14 +69,63 @@ def test_neohookean_128_bench_configuration():
     idx = rng.integers(0, F.reshape(-1, 3, 3).shape[0], 4096)
     Fs = F.reshape(-1, 3, 3)[idx]
     ls, ms = lam.reshape(-1)[idx], mu.reshape(-1)[idx]
-    assert rel(P.reshape(-1, 3, 3)[idx], materials.NeoHookean.stress(Fs, ls, ms)) < 1e-13
+    assert field_err(P.reshape(-1, 3, 3)[idx], materials.NeoHookean.stress(Fs, ls, ms)) < 1e-13
     # psi is O(strain^2) assembled from O(1) terms: its relative rounding is larger than P's
-    assert rel(E.reshape(-1)[idx], materials.NeoHookean.psi(Fs, ls, ms)) < 1e-12
+    assert field_err(E.reshape(-1)[idx], materials.NeoHookean.psi(Fs, ls, ms)) < 1e-12
     # equilibrium and compatibility, with the oracle's projection
     GP = spectral.apply_G(P, "finite")
     assert np.linalg.norm(GP) <= 1e-8 * np.linalg.norm(P)
     fl = F - Fbar
-    assert rel(spectral.apply_G(fl, "finite"), fl) < 1e-12
+    assert field_err(spectral.apply_G(fl, "finite"), fl) < 1e-12
+
+
+def test_neohookean_128_operator_and_rhs_elementwise_at_bench_shape(nh128):
+    """The CG operator q = G*(K(F):p) at the converged 128^3 state, and the Newton right-hand side
+    -G*(P(F)) of the next load step, element by element against the oracle, through the kernels and
+    the launch shape the benchmark times."""
+    w, h = nh128["w"], nh128["h"]
+    shape = w["shape"]
+    assert h.launch_shape() == BENCH_SHAPE_128
+    F = to_full(h.get_field(0), shape)
+    lam, mu = lame_fields(w["phase"], w["table"])
+    prob = newton_cg.Problem(shape, "neo_hookean", lam, mu)
+    rng = np.random.default_rng(11)
+    p = 1e-2 * rng.standard_normal(shape + (3, 3))
+    q = unpack(h.debug_apply_operator(pack(p, False)).cpu().numpy(), False, 3)
+    qref = prob.operator(F, p)
+    assert relmax(q, qref) < 1e-12 and rel(q, qref) < 1e-12
+    # stress everywhere, and the right-hand side of the first Newton step of a further increment
+    P = to_full(h.get_field(1), shape)
+    assert relmax(P, prob.stress(F)) < 1e-13
+    Fs = F.copy()
+    Fs[..., 0, 0] += 0.005
+    macro = w["macro"].copy()
+    macro[0] += 0.005
+    h.set_field(np.ascontiguousarray(np.moveaxis(Fs, (-2, -1), (0, 1)).reshape((9,) + shape)), macro)
+    Ps = to_full(h.get_field(1), shape)
+    b = h.debug_project(pack(-Ps, False)).cpu().numpy()
+    bref = prob.rhs(Fs)
+    assert relmax(unpack(b, False, 3), bref) < 1e-12
+    nh128["shifted"] = (Fs, macro, bref)
+
+
+def test_neohookean_128_first_cg_iterates_elementwise(nh128):
+    """The first CG iterates x_k and residuals r_k (k = 1, 3) of that Newton step, run by the
+    solver's own CG kernels at the benchmark's launch shape, against the oracle's textbook CG."""
+    w, h = nh128["w"], nh128["h"]
+    shape = w["shape"]
+    assert "shifted" in nh128, "runs after the operator test, which sets the shifted state"
+    Fs, macro, bref = nh128["shifted"]
+    lam, mu = lame_fields(w["phase"], w["table"])
+    prob = newton_cg.Problem(shape, "neo_hookean", lam, mu)
+    op = lambda v: prob.operator(Fs, v)  # noqa: E731
+    for k in (1, 3):
+        x, r = h.debug_cg(k)
+        xref, kk, status = newton_cg.conjugate_gradient(op, bref, 0.0, k)
+        assert kk == k and status == "not_converged"
+        rref = bref - op(xref)
+        assert field_err(unpack(x.cpu().numpy(), False, 3), xref) < 1e-11, k
+        assert field_err(unpack(r.cpu().numpy(), False, 3), rref) < 1e-11, k
 
 
 def test_spheres_64_tangent_properties():

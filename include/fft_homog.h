@@ -236,6 +236,28 @@ const char* fft_homog_strerror(int status);
  * fft_homog_create on the calling thread. */
 const char* fft_homog_last_error(const fft_homog_t* h);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, hosts that forbid hipMalloc.  out = G*in, the compatibility projection of the
+ * Fourier-Galerkin method (the same launches and results as fft_homog_debug_project on a handle
+ * of descriptor *d, which needs a workspace), without a handle or a workspace:
+ *   d          grid, kinematics and material as for fft_homog_create (material only selects the
+ *              component count: 3 / 6 small strain, 4 / 9 finite strain); flags, tolerances and
+ *              phases are ignored
+ *   in, out    device f64[batch][c][z][y][x], packed layout of the stage-level entry points
+ *              below; caller-owned; may not overlap
+ *   batch      >= 1 fields
+ *   hip_stream stream of the current device on which the work is enqueued (NULL = default).
+ * Enqueue only: nothing is synchronised and nothing is allocated; out is complete when the stream
+ * reaches this point.  Scratch (twiddle tables and the half spectrum, about
+ * batch * c * Ny * Nz * (Nx/2+1 rounded up to 8) * 16 bytes) lives in a 64 MiB device array that
+ * each device holds from library load to process end; larger requests return EWORKSPACE before
+ * touching the device.  Every call on a device shares that device's array: calls that overlap in
+ * time on one device (different streams, or different host threads) race and give wrong results.
+ * Errors: EINVAL / EUNSUPPORTED (descriptor, null pointers, batch < 1), EWORKSPACE, EDEVICE;
+ * fft_homog_last_error(NULL) describes the last failure on the calling thread. */
+int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double* out, int batch,
+                              void* hip_stream);
+
 /* ---- stage-level entry points (tests) --------------------------------------------------
  * Device arrays in the internal packed layout [batch][c][z][y][x]: c = ncomp, small strain
  * packed as Mandel components [11,22,33,sqrt2*23,sqrt2*13,sqrt2*12] (2D [11,22,sqrt2*12]),

@@ -84,6 +84,7 @@ EXPORTS = [
     "fft_homog_debug_cg_chunk", "fft_homog_debug_time_cg",
     "fft_homog_set_kernel_timing", "fft_homog_get_kernel_timing",
     "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune",
+    "fft_homog_project_noalloc",
 ]
 
 _lib = None
@@ -128,6 +129,7 @@ def load_library(path=LIB_PATH):
         "fft_homog_get_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_set_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_autotune": (I, [P, I, ctypes.POINTER(I)]),
+        "fft_homog_project_noalloc": (I, [ctypes.POINTER(Desc), P, P, I, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -420,6 +422,24 @@ def fft_homog_get_field(h, which):
 
 def fft_homog_set_field(h, full, macro):
     return h.set_field(full, macro)
+
+
+def fft_homog_project_noalloc(desc, x, out, stream=None):
+    """out = G*x through the allocation-free entry point: x and out are device float64 tensors of
+    shape (batch, c, *grid) (packed layout), enqueued on `stream` (default: the current stream)
+    with no synchronisation; raises FFTHomogError on a non-zero status."""
+    import torch
+
+    L = load_library()
+    assert x.dtype == torch.float64 and out.dtype == torch.float64 and x.is_contiguous() and out.is_contiguous()
+    assert x.shape == out.shape and x.dim() >= 2
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    rc = L.fft_homog_project_noalloc(ctypes.byref(desc), _tptr(x), _tptr(out), int(x.shape[0]),
+                                     ctypes.c_void_p(s.cuda_stream))
+    if rc:
+        msg = L.fft_homog_last_error(None)
+        raise FFTHomogError(rc, "fft_homog_project_noalloc: " + (msg.decode() if msg else ""))
+    return out
 
 
 def fft_homog_get_launch_shape(h):

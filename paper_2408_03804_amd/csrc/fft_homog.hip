@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,13 @@
 
 using namespace fh;
 
+// Scratch of the allocation-free projection (fft_homog_project_noalloc): the three twiddle
+// tables and the half spectrum.  A file-scope device array: every device the library runs on
+// holds its own copy from module load until the process ends.  Host code never uses this name
+// as an address (on the host it is only a stand-in); it uses the per-device address that
+// hipGetSymbolAddress returns.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -280,6 +288,28 @@ hipError_t enqueue_projection(const Geom& g, const AxisPlan* pl, const Layout& L
     e = launch_xinv(CONS_IDENT, ai, batch, s);
   }
   return e;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];  // address of `scratch` on each device, once looked up
+
+// Device address of `scratch` on the current device, looked up (hipGetSymbolAddress) on the
+// first call with that device current and kept.
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -1508,6 +1538,48 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
                            std::max(mid_smem(g, h->L.TXm, h->L.in_m, mid_planes(g, h->plan[1], h->L.TXm, h->L.in_m, h->L.B)),
                                     outer_smem(g, h->L.TXo, h->L.in_o)));
   if (shape) fft_homog_get_launch_shape(h, shape);
+  return FFT_HOMOG_OK;
+}
+
+int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double* out, int batch, void* hip_stream) {
+  if (!in || !out || batch < 1) return create_fail(FFT_HOMOG_EINVAL, "null field or batch < 1", hipSuccess);
+  Layout L;
+  const int rc = make_layout(d, &L);
+  if (rc) return create_fail(rc, "invalid or unsupported descriptor", hipSuccess);
+  Geom g;
+  make_geom(d, &g);
+  // scratch: twiddle tables of the axes, then the half spectrum [batch][c][z][y][pitch]
+  size_t off = 0;
+  size_t tw_off[3] = {0, 0, 0};
+  for (int a = 0; a < d->ndim; ++a) {
+    tw_off[a] = off;
+    off = align_up(off + (size_t)d->n[a] * sizeof(double2));
+  }
+  const size_t spec_off = off;
+  const size_t need = spec_off + (size_t)batch * g.c * g.Nh * sizeof(double2);
+  if (need > kNoAllocScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof(msg), "needs %zu bytes of scratch; the allocation-free projection has %zu per device",
+             need, kNoAllocScratchBytes);
+    return create_fail(FFT_HOMOG_EWORKSPACE, msg, hipSuccess);
+  }
+  char* base = nullptr;
+  hipError_t e = scratch_address((void**)&base);
+  if (e != hipSuccess) return create_fail(FFT_HOMOG_EDEVICE, "hipGetSymbolAddress(scratch)", e);
+  const hipStream_t s = (hipStream_t)hip_stream;
+  AxisPlan pl[3];
+  for (int a = 0; a < 3; ++a) {
+    pl[a].n = a < d->ndim ? d->n[a] : 1;
+    factorize(pl[a].n, pl[a].radix, &pl[a].nstages);
+    pl[a].tw = a < d->ndim ? (const double2*)(base + tw_off[a]) : nullptr;
+    if (a < d->ndim && e == hipSuccess) e = launch_twiddles((double2*)(base + tw_off[a]), d->n[a], s);
+  }
+  if (d->ndim == 2) pl[2] = pl[1];
+  const int matcode = 2 * d->material + (d->ndim - 2);
+  if (e == hipSuccess) e = set_smem_limits(g, matcode, L.smem_max);
+  if (e == hipSuccess) e = enqueue_projection(g, pl, L, matcode, in, out, (double2*)(base + spec_off), batch, s);
+  if (e != hipSuccess) return create_fail(FFT_HOMOG_EDEVICE, "projection launch", e);
+  g_create_err[0] = 0;
   return FFT_HOMOG_OK;
 }
 

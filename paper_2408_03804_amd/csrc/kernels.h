@@ -104,6 +104,8 @@ hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipS
 hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s);
 hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* full_out, double* energy_out,
                                const Geom& g, hipStream_t s);
+// twiddle table tw[m] = exp(-2 pi i m / n), m < n, computed on the device
+hipError_t launch_twiddles(double2* tw, int n, hipStream_t s);
 hipError_t launch_simp_scale(const double* density, double p, double* scale, long long N, hipStream_t s);
 hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s);
 hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE,

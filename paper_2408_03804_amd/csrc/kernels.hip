@@ -968,6 +968,16 @@ __global__ void __launch_bounds__(kThreads) k_simp_gradient(const double* F, con
 }
 
 // scale[v] = density[v]^p (SIMP interpolation of the Lame parameters)
+// tw[m] = exp(-2 pi i m / n), m < n (twiddle table of one FFT axis computed on the device)
+__global__ void k_twiddles(double2* tw, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+    tw[m] = make_double2(cs, -sn);
+  }
+}
+
 __global__ void k_simp_scale(const double* density, double p, double* scale, long long N) {
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x)
     scale[v] = pow(density[v], p);
@@ -1237,6 +1247,11 @@ hipError_t launch_simp_gradient(int mat, const double* F, const double* x, MatPa
                      w_energy, grad, g)
   FH_DISPATCH_MAT(mat, FH_L)
 #undef FH_L
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(double2* tw, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, tw, n);
   return hipGetLastError();
 }
 

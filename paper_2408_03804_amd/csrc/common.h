@@ -48,6 +48,11 @@ struct FastDiv {
 __host__ __device__ inline FastDiv make_fastdiv(unsigned d) { return FastDiv{d, d > 1 ? 0xFFFFFFFFu / d + 1u : 0u}; }
 __device__ __forceinline__ unsigned fdiv(unsigned w, FastDiv f) { return f.d > 1 ? __umulhi(w, f.m) : w; }
 
+// Tiles of kx bins of the y and outer passes: nxh bins in tiles of TX, tile b starting at bin b * TX.
+__host__ __device__ inline int kx_tiles(int nxh, int TX) { return (nxh + TX - 1) / TX; }
+__host__ __device__ inline int kx_tile_width(int nxh, int TX, int b) { return b * TX + TX <= nxh ? TX : nxh - b * TX; }
+__host__ __device__ inline int kx_tile_max(int nxh, int TX) { return TX < nxh ? TX : nxh; }
+
 // Factorisation of one FFT axis into Stockham stages and its twiddle table
 // tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device memory, host-computed in
 // extended precision).

@@ -129,6 +129,21 @@ int validate_desc(const fft_homog_desc* d) {
   return FFT_HOMOG_OK;
 }
 
+// Largest dynamic LDS of any pass at the launch shape of L: the projection chain's y and outer
+// kernels, and the plain transforms of the stage-level FFT entry points (which may carry more
+// components per block and fall back to the ping-pong buffer).
+size_t smem_needed(const Geom& g, const AxisPlan* pl, const Layout& L) {
+  size_t m = std::max(xfwd_smem(g, L.R, L.in_x), xinv_smem(g, L.R, L.in_x));
+  if (g.ndim == 3) {
+    m = std::max(m, mid_smem(g, L.TXm, L.in_m, mid_planes(g, pl[1], L.TXm, L.in_m, L.B, 1), 1));
+    m = std::max(m, mid_smem(g, L.TXm, L.in_m, mid_planes(g, pl[1], L.TXm, L.in_m, L.B, 0), 0));
+  }
+  m = std::max(m, outer_smem(g, L.TXo, L.in_o, OUTER_PROJECT));
+  // plain transforms narrow their tile to 64 KiB of LDS, down to one bin
+  m = std::max(m, std::min(outer_smem(g, L.TXo, 0, OUTER_FWD), std::max((size_t)64 * 1024, outer_smem(g, 1, 0, OUTER_FWD))));
+  return m;
+}
+
 int make_layout(const fft_homog_desc* d, Layout* L) {
   int rc = validate_desc(d);
   if (rc) return rc;
@@ -174,36 +189,39 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   }
   L->R = R;
   L->in_x = inx;
+  // y pass: sized for the projection chain's kernel (row-wise for finite strain 3D: three
+  // components per block)
+  const int ypr = finite_rows(g) ? 3 : C;
   int TXm = 0, inm = 0;
-  for (int t = par_cap((long long)g.nxh * g.nz * C, 16); t >= 1; --t) {
+  for (int t = par_cap((long long)g.nxh * g.nz * ypr, 16); t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
-    const int ip = inplace_ok(pl[1], t) ? 1 : 0;
-    if (mid_smem(g, t, ip) <= kLdsFft) { TXm = t; inm = ip; break; }
+    const int ip = inplace_ok(pl[1], mid_sequences(g, t, 1, 1)) ? 1 : 0;
+    if (mid_smem(g, t, ip, 1, 1) <= kLdsFft && mid_fits(g, t, 1, 1)) { TXm = t; inm = ip; break; }
   }
   if (TXm == 0) {
     TXm = 1;
-    inm = inplace_ok(pl[1], 1) ? 1 : 0;
-    if (mid_smem(g, 1, inm) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
+    inm = inplace_ok(pl[1], mid_sequences(g, 1, 1, 1)) ? 1 : 0;
+    if (mid_smem(g, 1, inm, 1, 1) > kLdsMax || !mid_fits(g, 1, 1, 1)) return FFT_HOMOG_EUNSUPPORTED;
   }
   L->TXm = TXm;
   L->in_m = inm;
-  const int G = outer_group(g);
+  // outer tile: the finite-strain row-wise projection moves two components per block and takes
+  // whole 128-byte lines (8 bins); the other outer passes take 4 bins
+  const int otmax = finite_rows(g) ? 2 * kOuterTileMax : kOuterTileMax;
   int TXo = 0, ino = 0;
-  for (int t = par_cap((long long)g.nxh * g.n_mid * (C / G), kOuterTileMax); t >= 1; --t) {
+  for (int t = par_cap((long long)g.nxh * g.n_mid * outer_groups_per_rhs(g), otmax); t >= 1; --t) {
     if (t > g.nxh && t > 1) continue;
-    const int ip = inplace_ok(pouter, G * t) ? 1 : 0;
-    if (t <= kOuterTileMax && outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }
+    const int ip = outer_inplace_ok(g, pouter, t) ? 1 : 0;
+    if (t <= otmax && outer_smem(g, t, ip) <= kLdsOuter) { TXo = t; ino = ip; break; }
   }
   if (TXo == 0) {
     TXo = 1;
-    ino = inplace_ok(pouter, G) ? 1 : 0;
+    ino = outer_inplace_ok(g, pouter, 1) ? 1 : 0;
     if (outer_smem(g, 1, ino) > kLdsMax) return FFT_HOMOG_EUNSUPPORTED;
   }
   L->TXo = TXo;
   L->in_o = ino;
-  L->smem_max = std::max(std::max(xfwd_smem(g, R, inx), xinv_smem(g, R, inx)),
-                         std::max(mid_smem(g, TXm, inm, mid_planes(g, pl[1], TXm, inm, L->B)),
-                                  outer_smem(g, TXo, ino)));
+  L->smem_max = smem_needed(g, pl, *L);
   L->nblk_x = (rows + R - 1) / R;
   L->nblk_vox = (int)((g.N + kThreads - 1) / kThreads);
 
@@ -265,7 +283,8 @@ hipError_t enqueue_projection(const Geom& g, const AxisPlan* pl, const Layout& L
     x.pl = pl[ax];
     x.TX = TX;
     x.inplace = inplace;
-    x.ZB = (ax == 1 && g.ndim == 3) ? mid_planes(g, pl[1], TX, inplace, L.B) : 1;
+    x.proj = 1;
+    x.ZB = (ax == 1 && g.ndim == 3) ? mid_planes(g, pl[1], TX, inplace, L.B, 1) : 1;
     x.spec = spec;
     return x;
   };
@@ -415,13 +434,15 @@ XInvArgs xinv_args(fft_homog_t* h) {
   return a;
 }
 
-AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inplace = -1) {
+// proj: the pass belongs to a projection chain (y pass: the row-wise finite-strain kernels)
+AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inplace = -1, int proj = 1) {
   AxisArgs a;
   a.g = h->g;
   a.pl = h->plan[axis];
   a.TX = TX;
   a.inplace = inplace >= 0 ? inplace : (axis == 1 && h->g.ndim == 3) ? h->L.in_m : h->L.in_o;
-  a.ZB = (axis == 1 && h->g.ndim == 3) ? mid_planes(h->g, h->plan[1], TX, a.inplace, h->L.B) : 1;
+  a.proj = proj;
+  a.ZB = (axis == 1 && h->g.ndim == 3) ? mid_planes(h->g, h->plan[1], TX, a.inplace, h->L.B, proj) : 1;
   a.spec = h->spec;
   a.st = st;
   a.active = nullptr;
@@ -435,7 +456,7 @@ AxisArgs axis_args(fft_homog_t* h, int axis, int TX, const CgState* st, int inpl
 hipError_t enqueue_spectral(fft_homog_t* h, int mode, int B, const CgState* st, hipStream_t s,
                             const int* active = nullptr) {
   hipError_t e = hipSuccess;
-  AxisArgs am = axis_args(h, 1, h->L.TXm, st);
+  AxisArgs am = axis_args(h, 1, h->L.TXm, st, -1, mode == OUTER_PROJECT);
   AxisArgs ao = axis_args(h, h->g.ndim - 1, h->L.TXo, st);
   am.active = ao.active = active;
   if (h->g.ndim == 3 && mode != OUTER_INV) e = launch_mid(-1, am, B, s);
@@ -711,12 +732,14 @@ int apply_shape(fft_homog_t* h, const int* s) {
   if (R < 1 || R > 16 || R > rows || TXm < 1 || TXm > g.nxh || TXo < 1 || TXo > g.nxh) return FFT_HOMOG_EINVAL;
   if ((ix != 0 && ix != 1) || (im != 0 && im != 1) || (io != 0 && io != 1)) return FFT_HOMOG_EINVAL;
   if (ix && !inplace_ok(h->plan[0], (g.c * R + 1) / 2)) return FFT_HOMOG_EINVAL;
-  if (g.ndim == 3 && im && !inplace_ok(h->plan[1], TXm)) return FFT_HOMOG_EINVAL;
-  if (io && !inplace_ok(h->plan[g.ndim - 1], outer_group(g) * TXo)) return FFT_HOMOG_EINVAL;
+  if (g.ndim == 3 && im && !inplace_ok(h->plan[1], mid_sequences(g, TXm, 1, 1))) return FFT_HOMOG_EINVAL;
+  if (io && !outer_inplace_ok(g, h->plan[g.ndim - 1], TXo)) return FFT_HOMOG_EINVAL;
   const size_t lim = 64 * 1024;
   if (std::max(xfwd_smem(g, R, ix), xinv_smem(g, R, ix)) > lim && !(R == h->L.R && ix == h->L.in_x))
     return FFT_HOMOG_EINVAL;
-  if (g.ndim == 3 && mid_smem(g, TXm, im) > lim && !(TXm == h->L.TXm && im == h->L.in_m)) return FFT_HOMOG_EINVAL;
+  if (g.ndim == 3 && mid_smem(g, TXm, im, 1, 1) > lim && !(TXm == h->L.TXm && im == h->L.in_m))
+    return FFT_HOMOG_EINVAL;
+  if (g.ndim == 3 && !mid_fits(g, TXm, 1, 1)) return FFT_HOMOG_EINVAL;
   if (outer_smem(g, TXo, io) > lim && !(TXo == h->L.TXo && io == h->L.in_o)) return FFT_HOMOG_EINVAL;
   drop_graphs(h);
   h->g.nxp = pitch;
@@ -1487,8 +1510,8 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
           for (int ip = 1; ip >= 0; --ip) {
             const bool incumbent = (t == def.TXm && ip == def.in_m);
             if ((pass == 0) != incumbent) continue;
-            if (ip && !inplace_ok(h->plan[1], t)) continue;
-            if (!incumbent && mid_smem(g, t, ip) > kLdsTune) continue;
+            if (ip && !inplace_ok(h->plan[1], mid_sequences(g, t, 1, 1))) continue;
+            if (!incumbent && (mid_smem(g, t, ip, 1, 1) > kLdsTune || !mid_fits(g, t, 1, 1))) continue;
             const AxisArgs a = axis_args(h, 1, t, h->st, ip);
             double ms = 0.0;
             FH_CK(time_launches(h, reps, [&]() {
@@ -1502,14 +1525,13 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
     }
     // outer pass: kx bins per block
     {
-      const int G = outer_group(g);
       double bt = 0.0;
       for (int pass = 0; pass < 2; ++pass)
         for (int t = std::min(32, g.nxh); t >= 1; --t)
           for (int ip = 1; ip >= 0; --ip) {
             const bool incumbent = (t == def.TXo && ip == def.in_o);
             if ((pass == 0) != incumbent) continue;
-            if (ip && !inplace_ok(pouter, G * t)) continue;
+            if (ip && !outer_inplace_ok(g, pouter, t)) continue;
             if (!incumbent && outer_smem(g, t, ip) > kLdsTune) continue;
             const AxisArgs a = axis_args(h, g.ndim - 1, t, h->st, ip);
             double ms = 0.0;
@@ -1534,9 +1556,7 @@ int fft_homog_autotune(fft_homog_t* h, int reps, int* shape) {
   h->L.in_m = best.in_m;
   h->L.TXo = best.TXo;
   h->L.in_o = best.in_o;
-  h->L.smem_max = std::max(std::max(xfwd_smem(g, h->L.R, h->L.in_x), xinv_smem(g, h->L.R, h->L.in_x)),
-                           std::max(mid_smem(g, h->L.TXm, h->L.in_m, mid_planes(g, h->plan[1], h->L.TXm, h->L.in_m, h->L.B)),
-                                    outer_smem(g, h->L.TXo, h->L.in_o)));
+  h->L.smem_max = smem_needed(g, h->plan, h->L);
   if (shape) fft_homog_get_launch_shape(h, shape);
   return FFT_HOMOG_OK;
 }

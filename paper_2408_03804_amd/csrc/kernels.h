@@ -56,6 +56,8 @@ struct AxisArgs {
   int TX;                // kx bins per block
   int ZB;                // y pass: consecutive z planes per block (1 for the other passes)
   int inplace;
+  int proj;              // y pass inside the projection chain (finite strain 3D: the row-wise
+                         // y passes that carry two components per row to the outer pass)
   double2* spec;
   const CgState* st;     // nullable: skip right-hand sides whose CG is not running
   const int* active;     // nullable: right-hand side of each launch-index group
@@ -69,12 +71,25 @@ struct AxisArgs {
 // dynamic LDS bytes of each pass; `inplace` drops the ping-pong buffer
 size_t xfwd_smem(const Geom& g, int R, int inplace);
 size_t xinv_smem(const Geom& g, int R, int inplace);
-size_t mid_smem(const Geom& g, int TX, int inplace, int ZB = 1);
+// y pass; proj != 0: the projection chain's y pass (three tiles per block for finite strain 3D)
+size_t mid_smem(const Geom& g, int TX, int inplace, int ZB = 1, int proj = 0);
+// sequences of one FFT call of a y-pass block of TX bins and ZB planes
+int mid_sequences(const Geom& g, int TX, int ZB, int proj);
+// the row-wise finite-strain y pass holds kFrowHeld elements per thread: ny * TX * ZB must fit
+constexpr int kFrowHeld = 8;
+bool mid_fits(const Geom& g, int TX, int ZB, int proj);
 // z planes per y-pass block for a tile of TX bins: 1 unless the tile spans the whole stored row,
 // then as many as fit 32 KiB of LDS while the pass keeps about 512 blocks over B right-hand sides
-int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B);
-size_t outer_smem(const Geom& g, int TX, int inplace);
-int outer_group(const Geom& g);   // components transformed together in the outer pass
+int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B, int proj = 0);
+// outer pass: LDS bytes, components per block and blocks per right-hand side along z of the
+// grid, for the projection (mode OUTER_PROJECT) or a plain transform (OUTER_FWD / OUTER_INV)
+size_t outer_smem(const Geom& g, int TX, int inplace, int mode = OUTER_PROJECT);
+int outer_group(const Geom& g, int mode = OUTER_PROJECT);
+int outer_groups_per_rhs(const Geom& g, int mode = OUTER_PROJECT);
+// register staging possible for an outer-pass block of TX bins (widest tile)
+bool outer_inplace_ok(const Geom& g, const AxisPlan& pl, int TX, int mode = OUTER_PROJECT);
+// true if the y pass of the projection chain uses the row-wise finite-strain kernels
+inline bool finite_rows(const Geom& g) { return !g.small && g.ndim == 3; }
 // true if an in-place transform of nseq sequences of this plan fits the register staging
 bool inplace_ok(const AxisPlan& pl, int nseq);
 

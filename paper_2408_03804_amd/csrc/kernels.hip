@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   const int b = a.active ? a.active[vb] : vb;
   if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
   const int kx0 = blockIdx.x * a.TX;
-  const int tw = min(a.TX, g.nxh - kx0);
+  const int tw = kx_tile_width(g.nxh, a.TX, blockIdx.x);
   const int ny = g.ny;
   const int z0 = blockIdx.y * a.ZB;
   const int nseq = min(a.ZB, g.nz - z0) * tw;
@@ -469,6 +469,24 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
     const int zz = (int)fdiv((unsigned)q, fdt);
     const int s = q - zz * tw;
     a.spec[base + (long long)(zz * ny + y) * g.nxp + s] = A[t];
+  }
+}
+
+// Consecutive blocks are dealt round-robin to the 8 XCDs, each with its own L2.  Re-index the
+// grid so that the blocks one XCD receives are consecutive in (x, y, z): neighbouring kx tiles of
+// a spectrum row, which share 128-byte lines when a tile is not a whole number of lines, then run
+// on the same XCD close in time and meet in its L2.
+__device__ __forceinline__ void xcd_blocks(unsigned* bx, unsigned* by, unsigned* bz) {
+  *bx = blockIdx.x;
+  *by = blockIdx.y;
+  *bz = blockIdx.z;
+  const unsigned tot = gridDim.x * gridDim.y * gridDim.z;
+  if ((tot & 7u) == 0u) {
+    const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned l2 = (lin & 7u) * (tot >> 3) + (lin >> 3);
+    *bx = l2 % gridDim.x;
+    *by = (l2 / gridDim.x) % gridDim.y;
+    *bz = l2 / (gridDim.x * gridDim.y);
   }
 }
 
@@ -559,20 +577,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
   constexpr int G = SMALL ? C : NDIM;
   constexpr int NGRP = C / G;
   const Geom& g = a.g;
-  // Consecutive blocks are dealt round-robin to the 8 XCDs.  Re-index so that
-  // the tiles of one spectrum row (which share 128-byte lines when TX < 8) run
-  // on the same XCD, close in time, and meet in its L2.
-  unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-  {
-    const unsigned tot = gridDim.x * gridDim.y * gridDim.z;
-    if ((tot & 7u) == 0u) {
-      const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-      const unsigned l2 = (lin & 7u) * (tot >> 3) + (lin >> 3);
-      bx = l2 % gridDim.x;
-      by = (l2 / gridDim.x) % gridDim.y;
-      bz = l2 / (gridDim.x * gridDim.y);
-    }
-  }
+  unsigned bx, by, bz;
+  xcd_blocks(&bx, &by, &bz);
   const int vb = bz / NGRP;
   const int grp = bz - vb * NGRP;
   const int b = a.active ? a.active[vb] : vb;
@@ -588,7 +594,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     if (threadIdx.x == 0) cg_finalize<RED_PQ>(a.pq_st[b], s);
   }
   const int kx0 = bx * a.TX;
-  const int tw = min(a.TX, g.nxh - kx0);
+  const int tw = kx_tile_width(g.nxh, a.TX, (int)bx);
   const int mid = by;
   const int n = g.n_outer;
   const int nseq = G * tw;
@@ -668,6 +674,218 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     const int jj = (int)fdiv((unsigned)rem, fdt);
     const int s = rem - jj * tw;
     a.spec[cbase + (long long)jj * g.Nh + base0 + o * ostride + s] = D[t];
+  }
+}
+
+// ============================================================================
+// finite strain, 3D: the projection chain row by row
+// ============================================================================
+// G-hat maps a row a_i = (a_i0, a_i1, a_i2) of A-hat to s_i xi with s_i = (a_i . xi) / |xi|^2
+// ((A n) (x) n with n = xi / |xi|).  xi_x depends only on kx and xi_y only on ky, so both factors
+// commute with the transforms along the other axes: the forward y pass already combines
+// v_i = xi_x a_i0 + xi_y a_i1 (w_i = a_i2 stays), the outer pass reads two components per row,
+// forms s_i = (v_i + xi_z w_i) / |xi|^2 and writes back s_i and xi_z s_i, and the inverse y pass
+// expands them to xi_x s_i, xi_y s_i, xi_z s_i.  The y and outer passes then move 15 + 12 + 15
+// instead of 18 + 18 + 18 component transfers per wavevector, and the outer pass transforms
+// 2 instead of 3 columns per row.  Slots: (i,0) carries v_i / s_i, (i,2) carries w_i / xi_z s_i.
+
+// y pass of row i = blockIdx.z mod 3 over a tile of TX bins and ZB planes, one component tile in
+// LDS at a time (the LDS and occupancy of a plain y pass); what the next phase combines is held in
+// registers, at most kFrowHeld elements per thread (the host keeps ny * TX * ZB <= kFrowHeld * 256).
+// Element y of sequence q = zz * tw + s at A[y * nseq + q]; thread t owns elements t + e * 256.
+//   DIR = -1: Y a_i0 -> held = xi_x Y a_i0;  Y a_i1 -> slot (i,0) = held + xi_y Y a_i1;
+//             Y a_i2 -> slot (i,2)
+//   DIR = +1: slot (i,0) = u -> held = xi_y u, Y^-1 u -> slot (i,0) = xi_x Y^-1 u;
+//             Y^-1 held -> slot (i,1);  slot (i,2) = w -> Y^-1 w -> slot (i,2)
+template <int DIR>
+// 4 waves per SIMD (at most 128 VGPRs; 157 unconstrained): measured 15 % faster at 128^3
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_mid_frow(AxisArgs a) {
+  const Geom& g = a.g;
+  unsigned bx, by, bz;
+  xcd_blocks(&bx, &by, &bz);
+  const int vb = bz / 3;
+  const int row = bz - vb * 3;
+  const int b = a.active ? a.active[vb] : vb;
+  if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
+  const int kx0 = bx * a.TX;
+  const int tw = kx_tile_width(g.nxh, a.TX, bx);
+  const int ny = g.ny;
+  const int z0 = by * a.ZB;
+  const int nseq = min(a.ZB, g.nz - z0) * tw;
+  const int cnt = ny * nseq;
+  extern __shared__ double2 smem[];
+  double2* A = smem;
+  double2* Bf = smem + (size_t)cnt;
+  const long long cbase = ((long long)b * 9 + row * 3) * g.Nh + (long long)z0 * ny * g.nxp + kx0;
+  const FastDiv fdq = make_fastdiv((unsigned)nseq);
+  const FastDiv fdt = make_fastdiv((unsigned)tw);
+  // global offset (within a component) and wavevector components of element t
+  auto where = [&](int t, long long* off, double* xx, double* xy) {
+    const int y = (int)fdiv((unsigned)t, fdq);
+    const int q = t - y * nseq;
+    const int zz = (int)fdiv((unsigned)q, fdt);
+    const int sx = q - zz * tw;
+    *off = (long long)(zz * ny + y) * g.nxp + sx;
+    *xx = signed_freq(kx0 + sx, g.nx, g.ks[0]);
+    *xy = signed_freq(y, ny, g.ks[1]);
+  };
+  auto load = [&](int slot) {
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      long long off;
+      double xx, xy;
+      where(t, &off, &xx, &xy);
+      A[t] = a.spec[cbase + slot * g.Nh + off];
+    }
+  };
+  auto store = [&](int slot) {
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      long long off;
+      double xx, xy;
+      where(t, &off, &xx, &xy);
+      a.spec[cbase + slot * g.Nh + off] = A[t];
+    }
+  };
+  double2 held[kFrowHeld];
+  if (DIR < 0) {
+    load(0);
+    __syncthreads();
+    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+#pragma unroll
+    for (int e = 0; e < kFrowHeld; ++e) {
+      const int t = threadIdx.x + e * blockDim.x;
+      if (t < cnt) {
+        long long off;
+        double xx, xy;
+        where(t, &off, &xx, &xy);
+        held[e] = make_double2(xx * A[t].x, xx * A[t].y);
+      }
+    }
+    __syncthreads();
+    load(1);
+    __syncthreads();
+    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+#pragma unroll
+    for (int e = 0; e < kFrowHeld; ++e) {
+      const int t = threadIdx.x + e * blockDim.x;
+      if (t < cnt) {
+        long long off;
+        double xx, xy;
+        where(t, &off, &xx, &xy);
+        const double2 v = A[t];
+        a.spec[cbase + off] = make_double2(held[e].x + xy * v.x, held[e].y + xy * v.y);
+      }
+    }
+    __syncthreads();
+    load(2);
+    __syncthreads();
+    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+    store(2);
+  } else {
+#pragma unroll
+    for (int e = 0; e < kFrowHeld; ++e) {
+      const int t = threadIdx.x + e * blockDim.x;
+      if (t < cnt) {
+        long long off;
+        double xx, xy;
+        where(t, &off, &xx, &xy);
+        const double2 u = a.spec[cbase + off];
+        A[t] = u;
+        held[e] = make_double2(xy * u.x, xy * u.y);
+      }
+    }
+    __syncthreads();
+    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      long long off;
+      double xx, xy;
+      where(t, &off, &xx, &xy);
+      a.spec[cbase + off] = make_double2(xx * A[t].x, xx * A[t].y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kFrowHeld; ++e) {
+      const int t = threadIdx.x + e * blockDim.x;
+      if (t < cnt) A[t] = held[e];
+    }
+    __syncthreads();
+    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    store(1);
+    __syncthreads();
+    load(2);
+    __syncthreads();
+    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    store(2);
+  }
+}
+
+// Outer (z) pass of the row-wise projection: row i = blockIdx.z mod 3 (after the XCD-aware
+// re-indexing), slots (i,0) = v and (i,2) = w of TX bins at one ky.  LDS: element o of sequence
+// (jj, s) at D[o * 2 tw + jj * tw + s].
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) k_outer_frow(AxisArgs a) {
+  const Geom& g = a.g;
+  unsigned bx, by, bz;
+  xcd_blocks(&bx, &by, &bz);
+  const int vb = bz / 3;
+  const int row = bz - vb * 3;
+  const int b = a.active ? a.active[vb] : vb;
+  if (a.st != nullptr && a.st[b].status != CG_RUNNING) return;
+  if (a.pq_st != nullptr && bx == 0 && by == 0 && row == 0) {
+    // <p, K:p> and alpha of right-hand side b, summed in a fixed order (read by the inverse x pass)
+    __shared__ double red[kThreads / 64];
+    const double* pp = a.pq_partials + (long long)b * a.pq_nblocks;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.pq_nblocks; i += blockDim.x) acc += pp[i];
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) cg_finalize<RED_PQ>(a.pq_st[b], sum);
+  }
+  const int kx0 = bx * a.TX;
+  const int tw = kx_tile_width(g.nxh, a.TX, (int)bx);
+  const int mid = by;
+  const int n = g.nz;
+  const int nseq = 2 * tw;
+  const int cnt = n * nseq;
+  extern __shared__ double2 smem[];
+  double2* D = smem;
+  double2* pong = smem + (size_t)cnt;
+  const long long ostride = (long long)g.ny * g.nxp;
+  const long long cbase = ((long long)b * 9 + row * 3) * g.Nh + (long long)mid * g.nxp + kx0;
+  const FastDiv fdq = make_fastdiv((unsigned)nseq);
+  const FastDiv fdt = make_fastdiv((unsigned)tw);
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int o = (int)fdiv((unsigned)t, fdq);
+    const int rem = t - o * nseq;
+    const int jj = (int)fdiv((unsigned)rem, fdt);
+    const int sx = rem - jj * tw;
+    D[t] = a.spec[cbase + 2 * jj * g.Nh + o * ostride + sx];
+  }
+  __syncthreads();
+  fft_lds_any<-1>(D, pong, nseq, a.pl, a.inplace);
+  const double xy = signed_freq(mid, g.ny, g.ks[1]);
+  for (int t = threadIdx.x; t < n * tw; t += blockDim.x) {
+    const int o = (int)fdiv((unsigned)t, fdt);
+    const int sx = t - o * tw;
+    const double xx = signed_freq(kx0 + sx, g.nx, g.ks[0]);
+    const double xz = signed_freq(o, n, g.ks[2]);
+    const double nrm2 = xx * xx + xy * xy + xz * xz;
+    const int e0 = o * nseq + sx;
+    double2 sv = make_double2(0.0, 0.0);
+    if (nrm2 > 0.0) {
+      const double inv = 1.0 / nrm2;
+      const double2 v = D[e0];
+      const double2 w = D[e0 + tw];
+      sv = make_double2((v.x + xz * w.x) * inv, (v.y + xz * w.y) * inv);
+    }
+    D[e0] = sv;
+    D[e0 + tw] = make_double2(xz * sv.x, xz * sv.y);
+  }
+  __syncthreads();
+  fft_lds_any<+1>(D, pong, nseq, a.pl, a.inplace);
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int o = (int)fdiv((unsigned)t, fdq);
+    const int rem = t - o * nseq;
+    const int jj = (int)fdiv((unsigned)rem, fdt);
+    const int sx = rem - jj * tw;
+    a.spec[cbase + 2 * jj * g.Nh + o * ostride + sx] = D[t];
   }
 }
 
@@ -1029,25 +1247,46 @@ size_t xinv_smem(const Geom& g, int R, int inplace) {
   if (h > bsz) bsz = h;
   return (a + bsz) * sizeof(double2);
 }
-size_t mid_smem(const Geom& g, int TX, int inplace, int ZB) {
-  return (inplace ? 1ull : 2ull) * g.ny * TX * ZB * sizeof(double2);
+int mid_sequences(const Geom& g, int TX, int ZB, int proj) {
+  (void)proj;  // the row-wise finite-strain y pass transforms one component tile at a time
+  return kx_tile_max(g.nxh, TX) * ZB;
 }
-int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B) {
-  if (g.ndim != 3 || TX < g.nxh) return 1;
+bool mid_fits(const Geom& g, int TX, int ZB, int proj) {
+  return !(proj && finite_rows(g)) || (long long)g.ny * kx_tile_max(g.nxh, TX) * ZB <= (long long)kFrowHeld * kThreads;
+}
+size_t mid_smem(const Geom& g, int TX, int inplace, int ZB, int proj) {
+  return (inplace ? 1ull : 2ull) * g.ny * mid_sequences(g, TX, ZB, proj) * sizeof(double2);
+}
+int mid_planes(const Geom& g, const AxisPlan& pl, int TX, int inplace, long long B, int proj) {
+  if (g.ndim != 3 || kx_tiles(g.nxh, TX) > 1) return 1;
   constexpr size_t kLdsPlanes = 32 * 1024;
   constexpr long long kBlocks = 512;
+  const int per_rhs = proj && finite_rows(g) ? 3 : g.c;
   int zb = 1;
   for (int z = 2; z <= std::min(8, g.nz); ++z) {
-    if (mid_smem(g, TX, inplace, z) > kLdsPlanes) break;
-    if (inplace && !inplace_ok(pl, z * TX)) break;
-    if ((long long)((g.nz + z - 1) / z) * g.c * B < kBlocks) break;
+    if (mid_smem(g, TX, inplace, z, proj) > kLdsPlanes || !mid_fits(g, TX, z, proj)) break;
+    if (inplace && !inplace_ok(pl, mid_sequences(g, TX, z, proj))) break;
+    if ((long long)((g.nz + z - 1) / z) * per_rhs * B < kBlocks) break;
     zb = z;
   }
   return zb;
 }
-int outer_group(const Geom& g) { return g.small ? g.c : g.ndim; }
-size_t outer_smem(const Geom& g, int TX, int inplace) {
-  return (size_t)(outer_group(g) * (inplace ? 1 : 2)) * g.n_outer * TX * sizeof(double2);
+// Projection: small strain couples all Mandel components of a wavevector; finite strain projects
+// each row of F on its own -- in 3D the row arrives as two components (see k_outer_frow), in 2D
+// as its two entries.  Plain transforms (debug FFTs) take whole rows (finite) or all components.
+int outer_group(const Geom& g, int mode) {
+  if (g.small) return g.c;
+  return (mode == OUTER_PROJECT && g.ndim == 3) ? 2 : g.ndim;
+}
+int outer_groups_per_rhs(const Geom& g, int mode) {
+  (void)mode;  // rows of F (finite strain) or one group of all components (small strain)
+  return g.small ? 1 : g.ndim;
+}
+size_t outer_smem(const Geom& g, int TX, int inplace, int mode) {
+  return (size_t)(outer_group(g, mode) * (inplace ? 1 : 2)) * g.n_outer * kx_tile_max(g.nxh, TX) * sizeof(double2);
+}
+bool outer_inplace_ok(const Geom& g, const AxisPlan& pl, int TX, int mode) {
+  return inplace_ok(pl, outer_group(g, mode) * kx_tile_max(g.nxh, TX));
 }
 bool inplace_ok(const AxisPlan& pl, int nseq) {
   for (int st = 0; st < pl.nstages; ++st) {
@@ -1103,16 +1342,39 @@ hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
 }
 
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
-  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, (a.g.nz + a.ZB - 1) / a.ZB, B * a.g.c);
-  const size_t sm = mid_smem(a.g, a.TX, a.inplace, a.ZB);
-  if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
-  else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
+  const bool rows = a.proj && finite_rows(a.g);
+  dim3 grid(kx_tiles(a.g.nxh, a.TX), (a.g.nz + a.ZB - 1) / a.ZB, B * (rows ? 3 : a.g.c));
+  const size_t sm = mid_smem(a.g, a.TX, a.inplace, a.ZB, a.proj);
+  if (rows) {
+    if (dir < 0) hipLaunchKernelGGL((k_mid_frow<-1>), grid, dim3(kThreads), sm, s, a);
+    else hipLaunchKernelGGL((k_mid_frow<1>), grid, dim3(kThreads), sm, s, a);
+  } else {
+    if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
+    else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_outer(int mode, const AxisArgs& a, int B, hipStream_t s) {
-  dim3 grid((a.g.nxh + a.TX - 1) / a.TX, a.g.n_mid, B * (a.g.c / outer_group(a.g)));
-  const size_t sm = outer_smem(a.g, a.TX, a.inplace);
+hipError_t launch_outer(int mode, const AxisArgs& a_in, int B, hipStream_t s) {
+  AxisArgs a = a_in;
+  const int G = outer_group(a.g, mode);
+  // a plain transform may carry more sequences per block than the projection the shape was
+  // chosen for: stage through the ping-pong buffer when they exceed the register staging, and
+  // narrow the tile while that needs more than 64 KiB of LDS (the grid follows the tile)
+  if (a.inplace && !outer_inplace_ok(a.g, a.pl, a.TX, mode)) a.inplace = 0;
+  if (mode != OUTER_PROJECT) {
+    while (a.TX > 1 && outer_smem(a.g, a.TX, a.inplace, mode) > 64 * 1024) {
+      a.TX = (a.TX + 1) / 2;
+      a.inplace = a_in.inplace && outer_inplace_ok(a.g, a.pl, a.TX, mode) ? 1 : 0;
+    }
+  }
+  (void)G;
+  dim3 grid(kx_tiles(a.g.nxh, a.TX), a.g.n_mid, B * outer_groups_per_rhs(a.g, mode));
+  const size_t sm = outer_smem(a.g, a.TX, a.inplace, mode);
+  if (mode == OUTER_PROJECT && finite_rows(a.g)) {
+    hipLaunchKernelGGL(k_outer_frow, grid, dim3(kThreads), sm, s, a);
+    return hipGetLastError();
+  }
 #define FH_L(SM, D)                                                                                          \
   switch (mode) {                                                                                            \
     case OUTER_PROJECT: hipLaunchKernelGGL((k_outer<OUTER_PROJECT, SM, D>), grid, dim3(kThreads), sm, s, a); break; \
@@ -1301,6 +1563,9 @@ hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes) {
 #undef FH_X
   FH_SET((k_mid<-1>));
   FH_SET((k_mid<1>));
+  FH_SET((k_mid_frow<-1>));
+  FH_SET((k_mid_frow<1>));
+  FH_SET(k_outer_frow);
 #define FH_O(SM, D) FH_SET((k_outer<OUTER_PROJECT, SM, D>)); FH_SET((k_outer<OUTER_FWD, SM, D>)); FH_SET((k_outer<OUTER_INV, SM, D>));
   if (g.small) {
     if (g.ndim == 3) { FH_O(1, 3) } else { FH_O(1, 2) }

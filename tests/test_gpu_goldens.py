@@ -14,6 +14,7 @@ import os
 import numpy as np
 import pytest
 
+from helpers import field_err
 from paper_2408_03804_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -48,3 +49,30 @@ def test_spheres_64_tangent_matches_oracle():
     assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
     for a, b in zip(st["cg"], g["cg_per_load"]):
         assert abs(a - b) <= 1, (st["cg"], g["cg_per_load"])
+
+
+@pytest.mark.parametrize("n", [64])
+def test_neohookean_grf_matches_oracle(n):
+    g = load("nh3d_grf_%d" % n)
+    smp = np.load(os.path.join(GOLDEN, "nh3d_grf_%d_samples.npz" % n))
+    w = workloads.workload_neohookean3d(n=n)
+    shape = w["shape"]
+    assert list(shape) == g["grid"] and abs(float(w["phase"].mean()) - g["stiff_fraction"]) == 0.0
+    h = make(shape, "finite", "neo_hookean", tol_newton=g["tol_newton"], tol_cg=g["tol_cg"], max_newton=50,
+             max_cg=20000)
+    h.set_material(w["phase"], w["table"])
+    S, psi, st = h.solve(w["macro"], w["n_increments"])
+    assert st["status"] == "ok"
+    # homogenized stress and energy
+    Sref = np.asarray(g["macro_stress"])
+    assert np.abs(S - Sref).max() < TOL_HOMOG * np.abs(Sref).max()
+    assert abs(psi - g["energy"]) < TOL_HOMOG * abs(g["energy"])
+    # iteration counts (the AD-vs-analytic identity: equal to within one at threshold crossings)
+    assert abs(st["newton"] - g["newton"]) <= 1
+    if st["newton"] == g["newton"]:
+        for a, b in zip(st["cg"], g["cg"]):
+            assert abs(a - b) <= 1, (st["cg"], g["cg"])
+    # the converged field at the seeded voxels, as fluctuations about the macro load
+    F = h.get_field(0).cpu().numpy().reshape(9, -1)[:, smp["index"]].T
+    Fbar = w["macro"].reshape(1, 9)
+    assert field_err(F - Fbar, smp["F"] - Fbar) < TOL_FIELD

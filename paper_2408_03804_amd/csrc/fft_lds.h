@@ -280,10 +280,11 @@ __device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nse
 
 // Same stage with the length, radix and stage position known at compile time
 // (no integer division except one magic multiply per element).
-template <int R, int NS, int N, int DIR>
+// MB: butterflies per thread (the host guarantees nseq * N / R <= MB * blockDim); MB = 1 keeps
+// one butterfly's values and twiddles live, which the kernels specialised for one length use.
+template <int R, int NS, int N, int DIR, int MB = kInplaceElems / R>
 __device__ __forceinline__ void stage_fixed(double2* __restrict__ buf, int nseq, FastDiv fd,
                                             const double2* __restrict__ tw) {
-  constexpr int MB = kInplaceElems / R;
   constexpr int NB = N / R;
   constexpr int STRIDE = N / (NS * R);
   const int total = NB * nseq;
@@ -324,13 +325,26 @@ __device__ __forceinline__ void stage_fixed(double2* __restrict__ buf, int nseq,
   __syncthreads();
 }
 
-template <int N, int DIR, int ST, int NS>
+template <int N, int DIR, int ST, int NS, bool ONE = false>
 __device__ __forceinline__ void fixed_stages(double2* buf, int nseq, FastDiv fd, const double2* tw) {
   if constexpr (ST < fixed_nstages(N)) {
     constexpr int R = fixed_radix(N, ST);
-    stage_fixed<R, NS, N, DIR>(buf, nseq, fd, tw);
-    fixed_stages<N, DIR, ST + 1, NS * R>(buf, nseq, fd, tw);
+    stage_fixed<R, NS, N, DIR, ONE ? 1 : kInplaceElems / R>(buf, nseq, fd, tw);
+    fixed_stages<N, DIR, ST + 1, NS * R, ONE>(buf, nseq, fd, tw);
   }
+}
+
+// In-place transform of length N (a compiled schedule) with one butterfly per thread per stage:
+// only that length's code and registers.  The caller guarantees fixed_one_ok(N, nseq).
+template <int N, int DIR>
+__device__ __forceinline__ void fft_fixed_one(double2* buf, int nseq, const double2* tw) {
+  fixed_stages<N, DIR, 0, 1, true>(buf, nseq, make_fastdiv((unsigned)nseq), tw);
+}
+__host__ __device__ inline bool fixed_one_ok(int n, int nseq) {
+  if (fixed_nstages(n) == 0) return false;
+  for (int st = 0; st < fixed_nstages(n); ++st)
+    if ((long long)nseq * (n / fixed_radix(n, st)) > kThreads) return false;
+  return true;
 }
 
 template <int DIR>

@@ -61,6 +61,15 @@ __device__ __forceinline__ void load_local(const MatParams& m, long long v, Loca
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// FFT of a pass.  NF > 0: a kernel specialised for axis length NF with one butterfly per thread per
+// stage -- only that length's code and a butterfly's registers (the launchers check fixed_one_ok);
+// NF = 0: any length, with the register staging or the ping-pong buffer the host chose.
+template <int D, int NF>
+__device__ __forceinline__ void pass_fft(double2* A, double2* Bf, int nseq, const AxisPlan& pl, int inplace) {
+  if constexpr (NF > 0) fft_fixed_one<NF, D>(A, nseq, pl.tw);
+  else fft_lds_any<D>(A, Bf, nseq, pl, inplace);
+}
+
 // Streaming access for the CG vectors and the linearisation point: each is touched once
 // per CG iteration, so keeping them out of the caches leaves room for the half spectrum
 // that the FFT passes hand to each other.
@@ -109,7 +118,7 @@ __device__ __forceinline__ void cg_finalize(CgState& S, double s) {
 // ============================================================================
 // x-axis forward pass
 // ============================================================================
-template <int PROD, int MAT, int NDIM>
+template <int PROD, int MAT, int NDIM, int NF = 0>
 __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   constexpr int C = MatTraits<MAT, NDIM>::C;
   constexpr bool CGOP = (PROD == PROD_CGOP || PROD == PROD_CGOP_STORED);
@@ -283,7 +292,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
   if (PROD == PROD_STRESS && bad) a.st[b].domain = 1;
   __syncthreads();
 
-  fft_lds_any<-1>(A, Bf, P, a.px, a.inplace);
+  pass_fft<-1, NF>(A, Bf, P, a.px, a.inplace);
   const double2* res = A;
 
   // separate the two real rows packed in each complex sequence
@@ -316,7 +325,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 // ============================================================================
 // x-axis inverse pass
 // ============================================================================
-template <int CONS, int C>
+template <int CONS, int C, int NF = 0>
 // 4 waves per SIMD (at most 128 VGPRs): measured 5 % faster at 128^3 than the unconstrained 166
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_xinv(XInvArgs a) {
   const int b = a.active ? a.active[blockIdx.y] : (int)blockIdx.y;
@@ -383,7 +392,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   }
   __syncthreads();
 
-  fft_lds_any<+1>(A, H, P, a.px, a.inplace);
+  pass_fft<1, NF>(A, H, P, a.px, a.inplace);
   const double2* res = A;
 
   double alpha = 0.0;
@@ -697,7 +706,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
 //             Y a_i2 -> slot (i,2)
 //   DIR = +1: slot (i,0) = u -> held = xi_y u, Y^-1 u -> slot (i,0) = xi_x Y^-1 u;
 //             Y^-1 held -> slot (i,1);  slot (i,2) = w -> Y^-1 w -> slot (i,2)
-template <int DIR>
+
+template <int DIR, int NF>
 // 4 waves per SIMD (at most 128 VGPRs; 157 unconstrained): measured 15 % faster at 128^3
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_mid_frow(AxisArgs a) {
   const Geom& g = a.g;
@@ -749,7 +759,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   if (DIR < 0) {
     load(0);
     __syncthreads();
-    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<-1, NF>(A, Bf, nseq, a.pl, a.inplace);
 #pragma unroll
     for (int e = 0; e < kFrowHeld; ++e) {
       const int t = threadIdx.x + e * blockDim.x;
@@ -763,7 +773,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     __syncthreads();
     load(1);
     __syncthreads();
-    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<-1, NF>(A, Bf, nseq, a.pl, a.inplace);
 #pragma unroll
     for (int e = 0; e < kFrowHeld; ++e) {
       const int t = threadIdx.x + e * blockDim.x;
@@ -778,7 +788,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     __syncthreads();
     load(2);
     __syncthreads();
-    fft_lds_any<-1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<-1, NF>(A, Bf, nseq, a.pl, a.inplace);
     store(2);
   } else {
 #pragma unroll
@@ -794,7 +804,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       }
     }
     __syncthreads();
-    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<1, NF>(A, Bf, nseq, a.pl, a.inplace);
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
       long long off;
       double xx, xy;
@@ -808,12 +818,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       if (t < cnt) A[t] = held[e];
     }
     __syncthreads();
-    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<1, NF>(A, Bf, nseq, a.pl, a.inplace);
     store(1);
     __syncthreads();
     load(2);
     __syncthreads();
-    fft_lds_any<+1>(A, Bf, nseq, a.pl, a.inplace);
+    pass_fft<1, NF>(A, Bf, nseq, a.pl, a.inplace);
     store(2);
   }
 }
@@ -821,6 +831,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
 // Outer (z) pass of the row-wise projection: row i = blockIdx.z mod 3 (after the XCD-aware
 // re-indexing), slots (i,0) = v and (i,2) = w of TX bins at one ky.  LDS: element o of sequence
 // (jj, s) at D[o * 2 tw + jj * tw + s].
+template <int NF>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) k_outer_frow(AxisArgs a) {
   const Geom& g = a.g;
   unsigned bx, by, bz;
@@ -859,7 +870,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     D[t] = a.spec[cbase + 2 * jj * g.Nh + o * ostride + sx];
   }
   __syncthreads();
-  fft_lds_any<-1>(D, pong, nseq, a.pl, a.inplace);
+  pass_fft<-1, NF>(D, pong, nseq, a.pl, a.inplace);
   const double xy = signed_freq(mid, g.ny, g.ks[1]);
   for (int t = threadIdx.x; t < n * tw; t += blockDim.x) {
     const int o = (int)fdiv((unsigned)t, fdt);
@@ -879,7 +890,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     D[e0 + tw] = make_double2(xz * sv.x, xz * sv.y);
   }
   __syncthreads();
-  fft_lds_any<+1>(D, pong, nseq, a.pl, a.inplace);
+  pass_fft<1, NF>(D, pong, nseq, a.pl, a.inplace);
   for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
     const int o = (int)fdiv((unsigned)t, fdq);
     const int rem = t - o * nseq;
@@ -1301,9 +1312,20 @@ bool inplace_ok(const AxisPlan& pl, int nseq) {
 
 static inline int nblk_rows(const Geom& g, int R) { return (g.ny * g.nz + R - 1) / R; }
 
+// x passes whose rows hold the benchmark's length in 3D: the CG-loop kernels specialised for it
+static inline bool x_fixed128(const Geom& g, const AxisPlan& px, int R, int inplace) {
+  return inplace && g.ndim == 3 && px.n == 128 && fixed_one_ok(128, (g.c * R + 1) / 2);
+}
+
 hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s) {
   dim3 grid(nblk_rows(a.g, a.R), B);
   const size_t sm = xfwd_smem(a.g, a.R, a.inplace);
+  if (prod == PROD_CGOP && x_fixed128(a.g, a.px, a.R, a.inplace)) {
+#define FH_C(M, D) hipLaunchKernelGGL((k_xfwd<PROD_CGOP, M, D, (D == 3 ? 128 : 0)>), grid, dim3(kThreads), sm, s, a);
+    FH_DISPATCH_MAT(mat, FH_C)
+#undef FH_C
+    return hipGetLastError();
+  }
 #define FH_L(M, D)                                                                                       \
   switch (prod) {                                                                                        \
     case PROD_IDENT: hipLaunchKernelGGL((k_xfwd<PROD_IDENT, M, D>), grid, dim3(kThreads), sm, s, a); break;   \
@@ -1323,6 +1345,11 @@ hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t 
 hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
   dim3 grid(nblk_rows(a.g, a.R), B);
   const size_t sm = xinv_smem(a.g, a.R, a.inplace);
+  if (cons == CONS_CGUPD && x_fixed128(a.g, a.px, a.R, a.inplace) && (a.g.c == 9 || a.g.c == 6)) {
+    if (a.g.c == 9) hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 9, 128>), grid, dim3(kThreads), sm, s, a);
+    else hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 6, 128>), grid, dim3(kThreads), sm, s, a);
+    return hipGetLastError();
+  }
 #define FH_L(CC)                                                                                        \
   switch (cons) {                                                                                       \
     case CONS_IDENT: hipLaunchKernelGGL((k_xinv<CONS_IDENT, CC>), grid, dim3(kThreads), sm, s, a); break; \
@@ -1346,8 +1373,15 @@ hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
   dim3 grid(kx_tiles(a.g.nxh, a.TX), (a.g.nz + a.ZB - 1) / a.ZB, B * (rows ? 3 : a.g.c));
   const size_t sm = mid_smem(a.g, a.TX, a.inplace, a.ZB, a.proj);
   if (rows) {
-    if (dir < 0) hipLaunchKernelGGL((k_mid_frow<-1>), grid, dim3(kThreads), sm, s, a);
-    else hipLaunchKernelGGL((k_mid_frow<1>), grid, dim3(kThreads), sm, s, a);
+    // the benchmark's axis length gets its own kernels when every stage keeps one butterfly per thread
+    const bool f128 = a.inplace && a.pl.n == 128 && fixed_one_ok(128, mid_sequences(a.g, a.TX, a.ZB, a.proj));
+    if (dir < 0) {
+      if (f128) hipLaunchKernelGGL((k_mid_frow<-1, 128>), grid, dim3(kThreads), sm, s, a);
+      else hipLaunchKernelGGL((k_mid_frow<-1, 0>), grid, dim3(kThreads), sm, s, a);
+    } else {
+      if (f128) hipLaunchKernelGGL((k_mid_frow<1, 128>), grid, dim3(kThreads), sm, s, a);
+      else hipLaunchKernelGGL((k_mid_frow<1, 0>), grid, dim3(kThreads), sm, s, a);
+    }
   } else {
     if (dir < 0) hipLaunchKernelGGL((k_mid<-1>), grid, dim3(kThreads), sm, s, a);
     else hipLaunchKernelGGL((k_mid<1>), grid, dim3(kThreads), sm, s, a);
@@ -1368,11 +1402,13 @@ hipError_t launch_outer(int mode, const AxisArgs& a_in, int B, hipStream_t s) {
       a.inplace = a_in.inplace && outer_inplace_ok(a.g, a.pl, a.TX, mode) ? 1 : 0;
     }
   }
-  (void)G;
   dim3 grid(kx_tiles(a.g.nxh, a.TX), a.g.n_mid, B * outer_groups_per_rhs(a.g, mode));
   const size_t sm = outer_smem(a.g, a.TX, a.inplace, mode);
   if (mode == OUTER_PROJECT && finite_rows(a.g)) {
-    hipLaunchKernelGGL(k_outer_frow, grid, dim3(kThreads), sm, s, a);
+    if (a.inplace && a.pl.n == 128 && fixed_one_ok(128, G * kx_tile_max(a.g.nxh, a.TX)))
+      hipLaunchKernelGGL((k_outer_frow<128>), grid, dim3(kThreads), sm, s, a);
+    else
+      hipLaunchKernelGGL((k_outer_frow<0>), grid, dim3(kThreads), sm, s, a);
     return hipGetLastError();
   }
 #define FH_L(SM, D)                                                                                          \
@@ -1549,23 +1585,27 @@ hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes) {
   FH_SET((k_xfwd<PROD_CGOP, M, D>));                \
   FH_SET((k_xfwd<PROD_TRHS, M, D>));                \
   FH_SET((k_xfwd<PROD_CGOP_STORED, M, D>));         \
-  FH_SET((k_xfwd<PROD_ADJ, M, D>));
+  FH_SET((k_xfwd<PROD_ADJ, M, D>));                \
+  FH_SET((k_xfwd<PROD_CGOP, M, D, (D == 3 ? 128 : 0)>));
   FH_DISPATCH_MAT(mat, FH_L)
 #undef FH_L
 #define FH_X(CC) FH_SET((k_xinv<CONS_IDENT, CC>)); FH_SET((k_xinv<CONS_RHS, CC>)); FH_SET((k_xinv<CONS_CGUPD, CC>));
   switch (g.c) {
     case 3: FH_X(3); break;
     case 4: FH_X(4); break;
-    case 6: FH_X(6); break;
-    case 9: FH_X(9); break;
+    case 6: FH_X(6); FH_SET((k_xinv<CONS_CGUPD, 6, 128>)); break;
+    case 9: FH_X(9); FH_SET((k_xinv<CONS_CGUPD, 9, 128>)); break;
     default: break;
   }
 #undef FH_X
   FH_SET((k_mid<-1>));
   FH_SET((k_mid<1>));
-  FH_SET((k_mid_frow<-1>));
-  FH_SET((k_mid_frow<1>));
-  FH_SET(k_outer_frow);
+  FH_SET((k_mid_frow<-1, 0>));
+  FH_SET((k_mid_frow<1, 0>));
+  FH_SET((k_mid_frow<-1, 128>));
+  FH_SET((k_mid_frow<1, 128>));
+  FH_SET((k_outer_frow<0>));
+  FH_SET((k_outer_frow<128>));
 #define FH_O(SM, D) FH_SET((k_outer<OUTER_PROJECT, SM, D>)); FH_SET((k_outer<OUTER_FWD, SM, D>)); FH_SET((k_outer<OUTER_INV, SM, D>));
   if (g.small) {
     if (g.ndim == 3) { FH_O(1, 3) } else { FH_O(1, 2) }

@@ -70,28 +70,48 @@ def log(msg):
     sys.stderr.flush()
 
 
-def algorithmic_bytes_per_voxel(c, N, Nh, material_reads_strain=True):
+def algorithmic_bytes_per_voxel(c, N, Nh, material_reads_strain=True, rows=False):
     """HBM bytes per voxel each CG-iteration kernel must move at minimum (FP64).
 
     xfwd reads r, p, x, the linearisation point F and the phase id and writes
     p, x and the half spectrum; xinv reads the half spectrum and r and writes r;
-    the y and outer passes read and write the half spectrum once.
+    the y and outer passes read and write the half spectrum once.  rows: the 3D
+    finite-strain projection runs row by row, and between the y passes the
+    spectrum has two instead of three components per row of F (the forward y pass
+    reads 9 and writes 6 components, the outer pass reads and writes 6, the inverse
+    y pass reads 6 and writes 9).
     """
     f = 8.0 * c               # one packed field
     s = 16.0 * c * Nh / N     # one half spectrum (nx/2+1 bins per row), per voxel
     xfwd = 3 * f + (f if material_reads_strain else 0.0) + 1.0 + 2 * f + s
     mid = 2 * s
     outer = 2 * s
+    if rows:
+        mid = s + s * 2.0 / 3.0
+        outer = 2 * s * 2.0 / 3.0
     xinv = s + 2 * f
     return {"xfwd_cgop": xfwd, "reduce_pq": 0.0, "y_fwd": mid, "outer_project": outer, "y_inv": mid,
             "xinv_cgupdate": xinv, "reduce_rr": 0.0}
 
 
-def cpu_oracle_sample(w, iters):
-    """Time `iters` CG iterations of the CPU oracle on the first load increment of the workload."""
+# the survey's byte model of one CG iteration (c = 9, finite strain): 8 CG-vector fields, the
+# linearisation point and 4 half-spectrum transfers in a two-stage 3D FFT
+def survey_model_bytes_per_voxel(c, N, Nh):
+    return 8 * 8.0 * c + 8.0 * c + 4 * 16.0 * c * Nh / N
+
+
+def host_cores():
+    """Cores this process may run on (the box's share, not os.cpu_count())."""
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_oracle_sample(w, iters_all, iters_one):
+    """Time CG iterations of the CPU oracle on the first load increment of the workload: on all
+    the host cores this process may use (the FFTs multi-threaded; the oracle's element-wise NumPy
+    work stays on one thread), and on one thread."""
     from threadpoolctl import threadpool_limits
 
-    from oracle import newton_cg
+    from oracle import newton_cg, spectral
 
     shape = w["shape"]
     tab = np.asarray(w["table"])
@@ -100,16 +120,27 @@ def cpu_oracle_sample(w, iters):
     d = len(shape)
     Fbar = w["macro"].reshape(d, d)
     F1 = np.eye(d) + (Fbar - np.eye(d)) / w["n_increments"]
-    with threadpool_limits(limits=1):
-        field = prob.uniform(F1)
-        b = prob.rhs(field)
-        t0 = time.perf_counter()
-        _, k, st = newton_cg.conjugate_gradient(lambda v: prob.operator(field, v), b, 0.0, iters)
-        t1 = time.perf_counter()
+    field = prob.uniform(F1)
+    b = prob.rhs(field)
     N = prob.N
-    return {"value": N * k / (t1 - t0), "unit": "voxel-iter/s", "cores": 1, "kind": "oracle",
-            "sample": "%d CG iterations (operator G*(K:p) + textbook CG update) of the CPU oracle on the "
-                      "first load increment of the same %s workload, single thread, %.1f s" % (k, w["name"], t1 - t0)}
+    out = {}
+    for cores, iters in ((host_cores(), iters_all), (1, iters_one)):
+        spectral.FFT_WORKERS = cores
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            _, k, st = newton_cg.conjugate_gradient(lambda v: prob.operator(field, v), b, 0.0, iters)
+            t1 = time.perf_counter()
+        out[cores] = (N * k / (t1 - t0), k, t1 - t0)
+    spectral.FFT_WORKERS = 1
+    allc = host_cores()
+    v, k, t = out[allc]
+    v1, k1, t1 = out[1]
+    return {"value": v, "unit": "voxel-iter/s", "cores": allc, "kind": "oracle",
+            "sample": "%d CG iterations (operator G*(K:p) + textbook CG update) of the CPU oracle on the first "
+                      "load increment of the same %s workload, FFTs on %d threads (the host cores this process "
+                      "may use), %.1f s" % (k, w["name"], allc, t),
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": "%d CG iterations, one thread, %.1f s" % (k1, t1)}}
 
 
 def cpu_tangent_sample(cells, budget_s):
@@ -394,9 +425,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
-    ap.add_argument("--timing-every", type=int, default=8,
+    ap.add_argument("--timing-every", type=int, default=32,
                     help="sample every k-th CG iteration of the timed solves for the per-kernel times")
-    ap.add_argument("--cpu-iters", type=int, default=7)
+    ap.add_argument("--cpu-iters", type=int, default=7, help="CPU oracle CG iterations timed on all host cores")
+    ap.add_argument("--cpu-iters-one", type=int, default=5, help="... and on one thread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--k-mode", type=int, default=0)
     ap.add_argument("--train-cells", type=int, default=20000)
@@ -418,6 +450,9 @@ def main():
     ap.add_argument("--max-gb", type=float, default=96.0, help="workspace budget per multi-cell handle")
     ap.add_argument("--concurrent", action="store_true", help="many-cell workloads: run the size groups concurrently")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--increments", type=int, default=0,
+                    help="nh128: load increments per solve (0: the workload's 10); fewer only for short "
+                         "counter-collection runs, never for the reported metric")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -471,6 +506,8 @@ def main():
                            "(l=8) top 30%% stiff, E1, E2 ~ lognormal(0,0.5), nu=0.3, 6 unit loads each, CG tol 1e-10")
     n = args.n
     w = workloads.workload_neohookean3d(n=n)
+    if args.increments > 0:
+        w["n_increments"] = args.increments
     shape = w["shape"]
     N = n ** 3
     c = 9
@@ -521,27 +558,37 @@ def main():
         raise RuntimeError("no CG iteration was sampled for kernel timing")
     log("kernel ms (%d sampled CG iterations): " % samples + ", ".join("%s %.4f" % (k, v) for k, v in zip(KERNELS, ms)))
     Nh = (n // 2 + 1) * n * n
-    bpv = algorithmic_bytes_per_voxel(c, N, Nh, True)
+    bpv = algorithmic_bytes_per_voxel(c, N, Nh, True, rows=True)
     dom = int(np.argmax(ms))
     name = KERNELS[dom]
     achieved = bpv[name] * N / (ms[dom] * 1e-3) / 1e9
-    cg_ms = float(np.sum(ms))
+    events_ms = float(np.sum(ms))
+    # wall time per CG iteration of the whole timed solves (Newton-level work, host checks and
+    # launch gaps included): never below the kernels' own time
+    wall_ms = wall / total_cg * 1e3
     iter_bytes = sum(bpv.values()) * N
+    survey_bytes = survey_model_bytes_per_voxel(c, N, Nh) * N
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(name),
                 "kernel_ms": round(float(ms[dom]), 5),
                 "timing": "HIP events on the library stream inside the timed solves, every %d-th CG "
-                          "iteration (%d samples)" % (args.timing_every, samples),
+                          "iteration (%d samples); an interval runs from the previous launch's end event to "
+                          "this launch's end event" % (args.timing_every, samples),
                 "algorithmic_bytes_per_launch": int(bpv[name] * N),
-                "cg_iteration": {"ms": round(cg_ms, 5), "algorithmic_bytes": int(iter_bytes),
-                                 "achieved_GBs": round(iter_bytes / (cg_ms * 1e-3) / 1e9, 1),
+                "cg_iteration": {"ms_wall": round(wall_ms, 5), "ms_events": round(events_ms, 5),
+                                 "algorithmic_bytes": int(iter_bytes),
+                                 "achieved_GBs_wall": round(iter_bytes / (wall_ms * 1e-3) / 1e9, 1),
+                                 "frac_wall": round(iter_bytes / (wall_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "survey_model_bytes": int(survey_bytes),
+                                 "survey_model_frac_wall": round(survey_bytes / (wall_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "kernels_ms": {k: round(float(v), 5) for k, v in zip(KERNELS, ms)}}}
 
     cpu = None
     if not args.no_cpu:
-        log("timing the CPU oracle (%d CG iterations at %d^3)" % (args.cpu_iters, n))
-        cpu = cpu_oracle_sample(w, args.cpu_iters)
-        log("cpu oracle: %.3e voxel-iter/s" % cpu["value"])
+        log("timing the CPU oracle (%d + %d CG iterations at %d^3)" % (args.cpu_iters, args.cpu_iters_one, n))
+        cpu = cpu_oracle_sample(w, args.cpu_iters, args.cpu_iters_one)
+        log("cpu oracle: %.3e voxel-iter/s on %d cores, %.3e on one" % (cpu["value"], cpu["cores"],
+                                                                      cpu["single_thread"]["value"]))
 
     out = {
         "metric": "Newton-CG voxel-iters/s at 128^3 FP64",
@@ -558,7 +605,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"] + ": 3D finite-strain compressible Neo-Hookean, %d^3 voxels, Gaussian "
                    "random field (l=8 voxels) thresholded at 30%% stiff, mu 1 vs 20, lam=2mu, F-bar=diag(1.05,1,1) "
-                   "in 10 increments, Newton/CG tol 1e-10, tangent by dual-number JVP" % n,
+                   "in %d increments, Newton/CG tol 1e-10, tangent by dual-number JVP" % (n, w["n_increments"]),
                    "grid": [n, n, n], "n_increments": w["n_increments"], "k_mode": "stored" if args.k_mode else "recompute",
                    "launch_shape": shape_info, "graph": args.graph,
                    "cg_iterations_per_step": [s["cg_total"] for s in stats],

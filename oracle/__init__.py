@@ -10,7 +10,8 @@ Everything here is written for a reader who checks it against the paper
 automatic differentiation", arXiv:2408.03804) by eye:
 
 * full d x d tensors everywhere (no Voigt or Mandel packing inside the solver),
-* ``numpy.fft.fftn``/``ifftn`` on the full complex spectrum,
+* ``scipy.fft.fftn``/``ifftn`` on the full complex spectrum (one thread unless a timing run sets
+  ``spectral.FFT_WORKERS``),
 * closed-form stress and tangent (the paper's "analytical implementation"),
 * textbook conjugate gradients and the Newton loop of Appendix A, Algorithm 1.
 

@@ -22,6 +22,11 @@ ndim-1-a.  Fields have shape (*grid, d, d).
 """
 
 import numpy as np
+from scipy import fft as _fft
+
+# Threads of the library FFT (scipy.fft's pocketfft); the element-wise NumPy work is
+# single-threaded either way.  Changed only to time the oracle on several host cores.
+FFT_WORKERS = 1
 
 
 def axis_wavenumbers(n, length):
@@ -76,8 +81,8 @@ def apply_G(A, kinematics, lengths=None):
     shape = A.shape[:-2]
     axes = tuple(range(d))
     n = unit_wavevectors(shape, lengths)
-    Ahat = np.fft.fftn(A, axes=axes)
-    return np.fft.ifftn(project_modes(Ahat, n, kinematics), axes=axes).real
+    Ahat = _fft.fftn(A, axes=axes, workers=FFT_WORKERS)
+    return _fft.ifftn(project_modes(Ahat, n, kinematics), axes=axes, workers=FFT_WORKERS).real
 
 
 def inner(A, B):

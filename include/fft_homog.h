@@ -27,6 +27,16 @@
  *   macro out   stress in the same order without factors (small) / first Piola-Kirchhoff
  *               stress row-major (finite); tangent C_IJ = d out_I / d macro_J, row-major.
  *   ncomp       number of macro components: 3 / 6 (small, 2D / 3D), 4 / 9 (finite).
+ *
+ * Fixed behaviour (no descriptor switch):
+ *   Nyquist     on an even axis the Nyquist index k = n/2 gets a zero wavevector component
+ *               (the spectral derivative of the real trigonometric interpolant has no Nyquist
+ *               part); the projection stays an exact, Hermitian-consistent per-mode projection.
+ *               The paper only uses odd grids, where the rule never applies.
+ *   determinism every reduction (CG dot products, Newton norms, homogenized averages) sums in a
+ *               fixed order (wavefront shuffles, then fixed wave and block order; no atomics), so
+ *               a repeated call on the same inputs and launch shape is bitwise identical.
+ *   2D          plane strain unless FFT_HOMOG_FLAG_PLANE_STRESS (linear elasticity only).
  */
 #ifndef FFT_HOMOG_H
 #define FFT_HOMOG_H

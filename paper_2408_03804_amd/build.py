@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfft_homog.so")
-SOURCES = ["kernels.hip", "fft_homog.hip", "cnn.hip"]
+SOURCES = ["kernels.hip", "fft_homog.hip", "cnn.hip", "launch_geometry.cpp", "noalloc_scratch.hip"]
 HEADERS = ["common.h", "dual.h", "materials.h", "fft_lds.h", "kernels.h"]
 
 FLAGS = [
@@ -48,7 +48,7 @@ def build(verbose=False, extra_flags=()):
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(tmp, src.replace(".hip", ".o"))
+        obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc()] + FLAGS + PER_FILE.get(src, []) + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

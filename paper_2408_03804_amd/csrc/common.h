@@ -1,4 +1,4 @@
-// Types shared by the host driver and the kernels.
+// Types shared by the host driver and the kernels (host-compilable: no device-only code).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,13 +32,6 @@ __host__ __device__ constexpr int fixed_radix(int n, int st) {
        : 8;
 }
 
-// x is neither NaN nor +-Inf, decided on the exponent bits: the CG kernels are compiled with
-// finite-math assumptions (see build.py), under which a floating-point isfinite() or NaN
-// comparison may be folded away; integer tests are not.
-__device__ __forceinline__ bool finite_bits(double x) {
-  return (__double_as_longlong(x) & 0x7ff0000000000000LL) != 0x7ff0000000000000LL;
-}
-
 // Exact w / d for w * d < 2^32 with a precomputed multiplier m = floor(2^32 / d) + 1
 // (d = 1 has no 32-bit multiplier and is passed through).
 struct FastDiv {
@@ -46,7 +39,9 @@ struct FastDiv {
   unsigned m;
 };
 __host__ __device__ inline FastDiv make_fastdiv(unsigned d) { return FastDiv{d, d > 1 ? 0xFFFFFFFFu / d + 1u : 0u}; }
-__device__ __forceinline__ unsigned fdiv(unsigned w, FastDiv f) { return f.d > 1 ? __umulhi(w, f.m) : w; }
+
+// register-staged FFT stages hold at most this many elements per thread
+constexpr int kInplaceElems = 16;
 
 // Tiles of kx bins of the y and outer passes: nxh bins in tiles of TX, tile b starting at bin b * TX.
 __host__ __device__ inline int kx_tiles(int nxh, int TX) { return (nxh + TX - 1) / TX; }

@@ -9,7 +9,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,13 +18,6 @@
 
 using namespace fh;
 
-// Scratch of the allocation-free projection (fft_homog_project_noalloc): the three twiddle
-// tables and the half spectrum.  A file-scope device array: every device the library runs on
-// holds its own copy from module load until the process ends.  Host code never uses this name
-// as an address (on the host it is only a stand-in); it uses the per-device address that
-// hipGetSymbolAddress returns.
-constexpr size_t kNoAllocScratchBytes = 64ull << 20;
-static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -307,28 +299,6 @@ hipError_t enqueue_projection(const Geom& g, const AxisPlan* pl, const Layout& L
     e = launch_xinv(CONS_IDENT, ai, batch, s);
   }
   return e;
-}
-
-constexpr int kMaxDevices = 64;
-std::mutex g_scratch_mutex;
-void* g_scratch_ptr[kMaxDevices];  // address of `scratch` on each device, once looked up
-
-// Device address of `scratch` on the current device, looked up (hipGetSymbolAddress) on the
-// first call with that device current and kept.
-hipError_t scratch_address(void** out) {
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lock(g_scratch_mutex);
-  if (!g_scratch_ptr[dev]) {
-    void* ptr = nullptr;
-    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
-    if (e != hipSuccess) return e;
-    g_scratch_ptr[dev] = ptr;
-  }
-  *out = g_scratch_ptr[dev];
-  return hipSuccess;
 }
 
 }  // namespace
@@ -1584,7 +1554,7 @@ int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double*
     return create_fail(FFT_HOMOG_EWORKSPACE, msg, hipSuccess);
   }
   char* base = nullptr;
-  hipError_t e = scratch_address((void**)&base);
+  hipError_t e = noalloc_scratch_address((void**)&base);
   if (e != hipSuccess) return create_fail(FFT_HOMOG_EDEVICE, "hipGetSymbolAddress(scratch)", e);
   const hipStream_t s = (hipStream_t)hip_stream;
   AxisPlan pl[3];

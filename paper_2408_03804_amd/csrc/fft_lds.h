@@ -15,6 +15,15 @@
 
 namespace fh {
 
+// x is neither NaN nor +-Inf, decided on the exponent bits: the CG kernels are compiled with
+// finite-math assumptions (see build.py), under which a floating-point isfinite() or NaN
+// comparison may be folded away; integer tests are not.
+__device__ __forceinline__ bool finite_bits(double x) {
+  return (__double_as_longlong(x) & 0x7ff0000000000000LL) != 0x7ff0000000000000LL;
+}
+
+__device__ __forceinline__ unsigned fdiv(unsigned w, FastDiv f) { return f.d > 1 ? __umulhi(w, f.m) : w; }
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -235,7 +244,6 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
 // synchronises, then writes the outputs to their Stockham positions in the same
 // buffer.  Usable when all radices are 2/3/4/5/8 and no thread owns more than
 // kInplaceElems elements in a stage (checked by the host: inplace_ok()).
-constexpr int kInplaceElems = 16;
 
 // (Run-time length and stage position; the divisions by nseq and Ns are magic multiplies.)
 template <int R, int DIR>

@@ -135,4 +135,9 @@ hipError_t launch_j2_commit(int mat, const double* F, MatParams m, double* hist,
 hipError_t launch_j2_plastic(int mat, const double* F, MatParams m, double* out, const Geom& g, hipStream_t s);
 hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes);
 
+// Scratch of the allocation-free projection: a file-scope device array of this many bytes per
+// device (noalloc_scratch.hip); its address on the current device.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+hipError_t noalloc_scratch_address(void** out);
+
 }  // namespace fh

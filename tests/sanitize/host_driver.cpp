@@ -1,0 +1,128 @@
+// Host-only exercise of the C ABI's host logic under AddressSanitizer and UndefinedBehaviorSanitizer:
+// descriptor validation and workspace layout over many grids, the CG chunk policy, status strings
+// and the argument checks that every entry point makes before it touches a device.  Built from
+// the library's own sources with host-only compilation (no device code, no GPU needed) by
+// tests/test_host_sanitized.py; exits non-zero if an expectation fails.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <initializer_list>
+
+#include "fft_homog.h"
+
+static int failures = 0;
+#define EXPECT(cond)                                                        \
+  do {                                                                      \
+    if (!(cond)) {                                                          \
+      std::fprintf(stderr, "expectation failed: %s (line %d)\n", #cond, __LINE__); \
+      ++failures;                                                           \
+    }                                                                       \
+  } while (0)
+
+static fft_homog_desc make(int ndim, int nx, int ny, int nz, int kin, int mat) {
+  fft_homog_desc d;
+  std::memset(&d, 0, sizeof(d));
+  d.ndim = ndim;
+  d.n[0] = nx;
+  d.n[1] = ny;
+  d.n[2] = nz;
+  d.len[0] = d.len[1] = d.len[2] = 1.0;
+  d.kinematics = kin;
+  d.material = mat;
+  d.nphase = 2;
+  d.tol_newton = 1e-10;
+  d.tol_cg = 1e-10;
+  d.max_newton = 50;
+  d.max_cg = 1000;
+  d.k_mode = FFT_HOMOG_K_RECOMPUTE;
+  d.flags = 0;
+  d.batch = 1;
+  return d;
+}
+
+int main() {
+  // workspace sizes over grids with every radix path: powers of two, 3, 5, large primes, ragged
+  const int sizes[] = {1, 2, 3, 5, 7, 8, 12, 13, 16, 17, 31, 32, 33, 48, 64, 80, 96, 97, 128, 160, 192, 199, 256, 299};
+  const int kins[2] = {FFT_HOMOG_SMALL_STRAIN, FFT_HOMOG_FINITE_STRAIN};
+  const int mats[2][2] = {{FFT_HOMOG_LINEAR_ELASTIC, FFT_HOMOG_J2_PLASTIC}, {FFT_HOMOG_NEO_HOOKEAN, FFT_HOMOG_STVK}};
+  long long checked = 0;
+  for (int ndim = 2; ndim <= 3; ++ndim)
+    for (int k = 0; k < 2; ++k)
+      for (int m = 0; m < 2; ++m)
+        for (int a : sizes)
+          for (int b : {1, 7, 32, 33}) {
+            for (int flags : {0, (int)FFT_HOMOG_FLAG_TANGENT}) {
+              fft_homog_desc d = make(ndim, a, b, ndim == 3 ? (a % 5) + 1 : 1, kins[k], mats[k][m]);
+              d.flags = (unsigned)flags;
+              size_t bytes = 0;
+              const int rc = fft_homog_workspace_size(&d, &bytes);
+              EXPECT(rc == FFT_HOMOG_OK);
+              if (rc == FFT_HOMOG_OK) {
+                const long long N = (long long)a * b * (ndim == 3 ? (a % 5) + 1 : 1);
+                const int c = kins[k] == FFT_HOMOG_SMALL_STRAIN ? (ndim == 3 ? 6 : 3) : ndim * ndim;
+                EXPECT(bytes >= (size_t)(8 * c * N * 4));
+              }
+              ++checked;
+            }
+          }
+  // multi-cell handles
+  for (int cells : {2, 16, 1000}) {
+    fft_homog_desc d = make(3, 32, 32, 32, FFT_HOMOG_SMALL_STRAIN, FFT_HOMOG_LINEAR_ELASTIC);
+    d.flags = FFT_HOMOG_FLAG_TANGENT;
+    d.batch = cells;
+    size_t bytes = 0;
+    EXPECT(fft_homog_workspace_size(&d, &bytes) == FFT_HOMOG_OK);
+  }
+  // invalid descriptors are rejected on the host
+  {
+    fft_homog_desc d = make(3, 8, 8, 8, FFT_HOMOG_SMALL_STRAIN, FFT_HOMOG_LINEAR_ELASTIC);
+    size_t bytes = 0;
+    fft_homog_desc e = d; e.ndim = 4; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.n[1] = 0; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.n[0] = 5000; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EUNSUPPORTED);
+    e = d; e.len[2] = NAN; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.tol_cg = -1.0; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.nphase = 300; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.flags = 1u << 9; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.batch = 4; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EINVAL);
+    e = d; e.batch = 2000; e.flags = FFT_HOMOG_FLAG_TANGENT; EXPECT(fft_homog_workspace_size(&e, &bytes) == FFT_HOMOG_EUNSUPPORTED);
+    EXPECT(fft_homog_workspace_size(nullptr, &bytes) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_workspace_size(&d, nullptr) == FFT_HOMOG_EINVAL);
+    // create refuses a missing or short workspace before any device call
+    fft_homog_t* h = nullptr;
+    EXPECT(fft_homog_create(&d, nullptr, 0, nullptr, &h) == FFT_HOMOG_EWORKSPACE && h == nullptr);
+    EXPECT(std::strlen(fft_homog_last_error(nullptr)) > 0);
+    EXPECT(fft_homog_create(&d, (void*)256, 16, nullptr, &h) == FFT_HOMOG_EWORKSPACE);
+    EXPECT(fft_homog_create(&e, nullptr, 0, nullptr, &h) != FFT_HOMOG_OK);
+    EXPECT(fft_homog_create(&d, nullptr, 0, nullptr, nullptr) == FFT_HOMOG_EINVAL);
+    // the allocation-free projection refuses bad arguments and oversize requests before any launch
+    double dummy[4];
+    EXPECT(fft_homog_project_noalloc(&d, nullptr, dummy, 1, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_project_noalloc(&d, dummy, dummy, 0, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_project_noalloc(&e, dummy, dummy, 1, nullptr) != FFT_HOMOG_OK);
+    fft_homog_desc big = make(3, 128, 128, 128, FFT_HOMOG_FINITE_STRAIN, FFT_HOMOG_NEO_HOOKEAN);
+    EXPECT(fft_homog_project_noalloc(&big, dummy, dummy, 1, nullptr) == FFT_HOMOG_EWORKSPACE);
+    EXPECT(std::strstr(fft_homog_last_error(nullptr), "scratch") != nullptr);
+    // null handles
+    EXPECT(fft_homog_solve(nullptr, nullptr, 1, nullptr, nullptr, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_tangent(nullptr, nullptr, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_get_launch_shape(nullptr, nullptr) == FFT_HOMOG_EINVAL);
+    fft_homog_destroy(nullptr);
+  }
+  // status strings
+  for (int s = 0; s < 12; ++s) EXPECT(fft_homog_strerror(s) != nullptr);
+  // CG chunk policy: always 1..16 iterations, for any residual history (including NaN and Inf)
+  const double vals[] = {0.0, 1e-300, 1e-30, 1e-12, 0.5, 1.0, 2.0, 1e30, INFINITY, NAN, -1.0};
+  for (int it : {0, 1, 4, 5, 100, 1000000})
+    for (double rr0 : vals)
+      for (double rr : vals)
+        for (double tol : {1e-16, 1e-10, 0.5, 0.0})
+          for (int prev : {-1, 0, 3, it})
+            for (double prr : vals) {
+              const int m = fft_homog_debug_cg_chunk(it, rr0, rr, tol, prev, prr);
+              EXPECT(m >= 1 && m <= 16);
+            }
+  std::printf("host checks: %lld descriptors, %d failures\n", checked, failures);
+  return failures == 0 ? 0 : 1;
+}

@@ -241,24 +241,25 @@ def bench_surrogate(args):
     from paper_2408_03804_amd.batch import TangentBatcher
     from paper_2408_03804_amd.surrogate import StiffnessSurrogate, full6
 
-    ntr, nte = args.train_cells, args.test_cells
+    ntr, ncal, nte = args.train_cells, args.cal_cells, args.test_cells
     t0 = time.perf_counter()
-    cells = workloads.workload_tangent_cells(ntr + nte, seed=0)
+    cells = workloads.workload_tangent_cells(ntr + ncal + nte, seed=0)
     phase = torch.stack([torch.as_tensor(c["phase"]) for c in cells]).to("cuda:0")
     tables = np.stack([c["table"] for c in cells])
     del cells
-    log("%d cells generated in %.1f s" % (ntr + nte, time.perf_counter() - t0))
+    log("%d cells generated in %.1f s" % (ntr + ncal + nte, time.perf_counter() - t0))
 
     # training data and held-out references from the FP64 solver
     b = TangentBatcher(tol_cg=1e-10, max_cg=20000, graph=True, autotune=True, max_bytes=int(48 << 30),
                        device="cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    C_all, info = b.tangents([dict(phase=phase[i], table=tables[i]) for i in range(ntr + nte)])
+    C_all, info = b.tangents([dict(phase=phase[i], table=tables[i]) for i in range(ntr + ncal + nte)])
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     b.close()
-    log("solver tangents of %d cells: %.1f s (%.1f tangents/s)" % (ntr + nte, t_data, (ntr + nte) / t_data))
+    log("solver tangents of %d cells: %.1f s (%.1f tangents/s)" % (ntr + ncal + nte, t_data,
+                                                                   (ntr + ncal + nte) / t_data))
 
     sur = StiffnessSurrogate(n=32, max_batch=max(args.batch, nte), device="cuda:0", seed=0, members=args.members)
     t0 = time.perf_counter()
@@ -268,8 +269,27 @@ def bench_surrogate(args):
     t_train = time.perf_counter() - t0
     log("training: %.1f s, final losses %s" % (t_train, [h[-1] for h in hist]))
 
-    tp, tt, Ct = phase[ntr:], tables[ntr:], C_all[ntr:]
-    kw = dict(tol=args.check_tol, max_spread=args.max_spread)
+    # the indicator's spread limit from the calibration split (held out from training and from the report)
+    sur.tol = args.check_tol
+    cal = sur.calibrate(phase[ntr:ntr + ncal], tables[ntr:ntr + ncal], C_all[ntr:ntr + ncal], target=args.target,
+                        safety=args.safety)
+    log("calibration: %s" % cal)
+    if args.dump:
+        # per-cell indicator statistics of the calibration and test splits (analysis of the indicator)
+        dump = {}
+        for tag, sl in (("cal", slice(ntr, ntr + ncal)), ("test", slice(ntr + ncal, ntr + ncal + nte))):
+            Cq, okq, spq = sur.predict_checked(phase[sl], tables[sl], max_spread=1e30, want_spread=True)
+            Cf = full6(Cq.cpu().numpy().astype(np.float64))
+            Cr = C_all[sl]
+            dump[tag + "_err"] = np.linalg.norm((Cf - Cr).reshape(len(Cr), -1), axis=1) / np.linalg.norm(
+                Cr.reshape(len(Cr), -1), axis=1)
+            dump[tag + "_ok"] = okq.cpu().numpy()
+            dump[tag + "_spread"] = spq.cpu().numpy()
+            dump[tag + "_feat"] = StiffnessSurrogate.features(tables[sl])[:, 0]
+            dump[tag + "_frac"] = StiffnessSurrogate.fractions(phase[sl])
+        np.savez(args.dump, **dump)
+    tp, tt, Ct = phase[ntr + ncal:], tables[ntr + ncal:], C_all[ntr + ncal:]
+    kw = {}
     for _ in range(2):
         sur.predict_checked(tp, tt, **kw)
     torch.cuda.synchronize()
@@ -321,12 +341,15 @@ def bench_surrogate(args):
         "unit": "tangents/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": (t_sur + t_fb) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": "surrogate32: %d training + %d held-out small-strain linear elastic 32^3 cells "
-                               "(Gaussian random field l=8, top 30%% stiff, E1, E2 ~ lognormal(0,0.5), nu=0.3); "
-                               "CNN 1-32-64-128-256 stride-2 3^3 conv blocks, GELU, mean pool, MLP 257-256-21, "
-                               "bf16 MFMA / fp32 accumulation, Adam %d epochs batch %d, ensemble of %d, indicator: "
-                               "Voigt-Reuss bounds (tol %g), central 95%% of the training contrasts, member spread <= %g"
-                               % (ntr, nte, args.epochs, args.batch, args.members, args.check_tol, args.max_spread),
+        "config": {"workload": "surrogate32: %d training + %d calibration + %d held-out test small-strain linear "
+                               "elastic 32^3 cells (Gaussian random field l=8, top 30%% stiff, E1, E2 ~ "
+                               "lognormal(0,0.5), nu=0.3); CNN 1-32-64-128-256 stride-2 3^3 conv blocks, GELU, mean "
+                               "pool, MLP 257-256-21, bf16 MFMA / fp32 accumulation, Adam %d epochs batch %d, "
+                               "ensemble of %d, indicator: Voigt-Reuss bounds (tol %g), central 95%% of the training "
+                               "contrasts, member spread <= %.4g (calibrated: accepted calibration errors <= %g x %g)"
+                               % (ntr, ncal, nte, args.epochs, args.batch, args.members, args.check_tol,
+                                  sur.max_spread, args.safety, args.target),
+                   "calibration": cal,
                    "solver_tangents_per_s": nte / t_sol,
                    "surrogate_only_tangents_per_s": nte / t_sur,
                    "speedup_vs_solver": t_sol / (t_sur + t_fb),
@@ -334,7 +357,9 @@ def bench_surrogate(args):
                                            "p95": float(np.percentile(err, 95)), "max": float(err.max()),
                                            "frac_le_2pct": float((err <= 0.02).mean())},
                    "after_fallback": {"mean": float(final_err.mean()), "p95": float(np.percentile(final_err, 95)),
+                                      "max": float(final_err.max()),
                                       "frac_le_2pct": float((final_err <= 0.02).mean())},
+                   "accepted_fraction": float(okh.mean()),
                    "rejected_by_indicator": int((~okh).sum()),
                    "error_by_contrast_tercile": by_contrast,
                    "rejections_by_test": reasons,
@@ -436,8 +461,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--check-tol", type=float, default=0.02)
-    ap.add_argument("--max-spread", type=float, default=0.03)
+    ap.add_argument("--check-tol", type=float, default=0.02, help="surrogate: Voigt-Reuss bounds slack")
+    ap.add_argument("--cal-cells", type=int, default=1024, help="surrogate: calibration cells (held out)")
+    ap.add_argument("--dump", default="", help="surrogate: write per-cell indicator statistics to this .npz")
+    ap.add_argument("--target", type=float, default=0.02, help="surrogate: relative tangent error target")
+    ap.add_argument("--safety", type=float, default=0.8,
+                    help="surrogate: accepted calibration errors must stay below safety x target")
     ap.add_argument("--members", type=int, default=2)
     ap.add_argument("--workload", default="nh128",
                     choices=["nh128", "uq256", "tangents32", "surrogate32", "e2_stvk299", "e3_j2_199"],

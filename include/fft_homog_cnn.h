@@ -62,9 +62,10 @@ int fft_homog_cnn_get_params(fft_homog_cnn_t* h, float* params);
  *   phase      u8[batch][n^3], layout [z][y][x], values 0 or 1 (others EINVAL, checked on device)
  *   feat       f32[batch][n_feat] (NULL allowed when n_feat == 0)
  *   out_scale  f32[batch] or NULL: out[b][:] is multiplied by out_scale[b]
+ *   out_offset f32[batch][n_out] or NULL: then added, out = out_offset + out_scale * y
  *   out        f32[batch][n_out] */
 int fft_homog_cnn_forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat,
-                          const float* out_scale, float* out, int batch);
+                          const float* out_scale, const float* out_offset, float* out, int batch);
 
 /* Forward and backward pass: *loss (host) = mean over batch and outputs of (y - target)^2,
  * target f32[batch][n_out]; the gradient with respect to the flat parameters is kept in the
@@ -88,10 +89,12 @@ int fft_homog_cnn_adam_step(fft_homog_cnn_t* h, float lr, float beta1, float bet
  *   C2 (nullable, f32[batch][21]): the prediction of a second, independently trained network.
  *   C is then replaced in place by (C + C2) / 2, the tests above apply to that mean, and the
  *   spread |C - C2| / |(C + C2) / 2| (2-norms over the 21 components) must not exceed
- *   max_spread. */
+ *   max_spread.
+ *   spread_out (nullable, f32[batch]) receives that spread per sample (0 without C2), the
+ *   statistic a caller calibrates max_spread on (held-out samples with known tangents). */
 int fft_homog_cnn_check(fft_homog_cnn_t* h, const uint8_t* phase, const float* lam_mu,
                         const float* feat, float* C, const float* C2, int batch, float tol,
-                        float feat_lo, float feat_hi, float max_spread, int* ok);
+                        float feat_lo, float feat_hi, float max_spread, int* ok, float* spread_out);
 
 /* Device time (ms, HIP events) of the last forward and of the last loss_grad call. */
 int fft_homog_cnn_last_ms(const fft_homog_cnn_t* h, double* forward_ms, double* train_ms);

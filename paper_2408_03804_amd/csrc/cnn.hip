@@ -1,6 +1,6 @@
 // Voxel-CNN stiffness surrogate on the gfx950 matrix cores.
 //
-// Every layer is a bf16 x bf16 -> fp32 GEMM on MFMA 16x16x16 tiles:
+// Every layer is a bf16 x bf16 -> fp32 GEMM on gfx950 MFMA 16x16x32 tiles:
 //   conv forward      pre[m][co]   = col[m][k] . W[co][k]            (col = periodic stride-2 im2col)
 //   conv weight grad  dW[co][k]    = sum_m dpre[m][co] col[m][k]      (split over m, fixed-order sum)
 //   conv input grad   dcol[m][k]   = sum_co dpre[m][co] W[co][k], then a gather back to the voxels
@@ -21,7 +21,7 @@
 namespace cnn {
 
 typedef uint16_t bf16;
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
@@ -98,7 +98,8 @@ __device__ inline void load_tile(bf16 (*T)[LDT], const bf16* P, long long s_row,
 }
 
 // 256 threads = 4 waves in a 2 x 2 arrangement, each wave a 32 x 32 block of 2 x 2 MFMA tiles.
-// MFMA 16x16x16 bf16 operand layout: lane l holds rows/cols (l mod 16) at k = 4 (l / 16) + 0..3;
+// gfx950 MFMA 16x16x32 bf16 (v_mfma_f32_16x16x32_bf16, one instruction per 32-deep k step of a tile):
+// lane l holds rows/cols (l mod 16) at k = 8 (l / 16) + 0..7 (one 16-byte LDS read per operand);
 // the accumulator holds column (l mod 16), rows 4 (l / 16) + 0..3.
 template <bool AK, bool BK_>
 __global__ void __launch_bounds__(kT) k_gemm(GemmArgs g) {
@@ -113,7 +114,8 @@ __global__ void __launch_bounds__(kT) k_gemm(GemmArgs g) {
   const int wm = (w >> 1) * 32;
   const int wn = (w & 1) * 32;
   const int lr = lane & 15;
-  const int lk = 4 * (lane >> 4);
+  const int lk = 4 * (lane >> 4);   // accumulator rows
+  const int lk8 = 8 * (lane >> 4);  // operand k offset
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -123,18 +125,18 @@ __global__ void __launch_bounds__(kT) k_gemm(GemmArgs g) {
     load_tile<AK>(As, g.A, g.sam, g.sak, m0, g.M, k0, kend);
     load_tile<BK_>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, kend);
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      v4s a[2], b[2];
+    static_assert(BK == 32, "one 16x16x32 MFMA per k tile");
+    {
+      v8bf a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const v4s*>(&As[wm + 16 * i + lr][ks + lk]);
-        b[i] = *reinterpret_cast<const v4s*>(&Bs[wn + 16 * i + lr][ks + lk]);
+        a[i] = *reinterpret_cast<const v8bf*>(&As[wm + 16 * i + lr][lk8]);
+        b[i] = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 * i + lr][lk8]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -296,13 +298,16 @@ __global__ void k_pool_concat(const float* pre4, int B, int V, int C, const floa
 }
 
 // y[b][o] = (C[b][o] + bias[o]) * scale[b]
-__global__ void k_output(const float* C, const float* bias, const float* scale, int B, int O, float* y) {
+// y = offset + scale (C + bias) per sample (offset, scale nullable)
+__global__ void k_output(const float* C, const float* bias, const float* scale, const float* offset, int B, int O,
+                         float* y) {
   const long long tot = (long long)B * O;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(e / O);
     const int o = (int)(e - (long long)b * O);
     float v = C[e] + bias[o];
     if (scale) v *= scale[b];
+    if (offset) v += offset[e];
     y[e] = v;
   }
 }
@@ -532,7 +537,7 @@ __device__ void iso6(double lam, double mu, double (*C)[6]) {
 
 // one block per sample: volume fraction, Voigt / Reuss bounds, Cholesky tests, feature range
 __global__ void k_check(const uint8_t* phase, long long Nv, const float* lm, const float* feat, int nf, float* C21,
-                        const float* C2, float tol, float lo, float hi, float max_spread, int* ok) {
+                        const float* C2, float tol, float lo, float hi, float max_spread, int* ok, float* spread_out) {
   __shared__ double red[kT];
   const int b = blockIdx.x;
   double cnt = 0.0;
@@ -573,6 +578,7 @@ __global__ void k_check(const uint8_t* phase, long long Nv, const float* lm, con
     }
   bool good = spd6(Cp);
   if (C2) good = good && (sqrt(d2) <= (double)max_spread * sqrt(n2));
+  if (spread_out) spread_out[b] = C2 ? (float)(sqrt(d2) / fmax(sqrt(n2), 1e-300)) : 0.0f;
   // bounds with a slack of tol |C_Voigt|_F in every direction (prediction errors are measured
   // in that norm; a per-direction relative slack would reject small errors in the soft
   // shear directions)
@@ -907,7 +913,8 @@ int fft_homog_cnn_get_params(fft_homog_cnn_t* h, float* params) {
   return FFT_HOMOG_OK;
 }
 
-int fft_homog_cnn_forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat, const float* out_scale, float* out,
+int fft_homog_cnn_forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat, const float* out_scale,
+                          const float* out_offset, float* out,
                           int batch) {
   if (!h || !phase || !out || (h->d.n_feat > 0 && !feat)) return FFT_HOMOG_EINVAL;
   if (check_batch(h, batch)) return FFT_HOMOG_EINVAL;
@@ -915,7 +922,7 @@ int fft_homog_cnn_forward(fft_homog_cnn_t* h, const uint8_t* phase, const float*
   int rc = forward(h, phase, feat, batch);
   if (rc) return rc;
   hipLaunchKernelGGL(k_output, dim3(blocks((long long)batch * h->d.n_out)), dim3(kT), 0, h->s, h->scratch,
-                     h->p + h->offB[6], out_scale, batch, h->d.n_out, out);
+                     h->p + h->offB[6], out_scale, out_offset, batch, h->d.n_out, out);
   CK(hipGetLastError());
   CK(hipEventRecord(h->e1, h->s));
   rc = read_flag(h);
@@ -935,7 +942,7 @@ int fft_homog_cnn_loss_grad(fft_homog_cnn_t* h, const uint8_t* phase, const floa
   int rc = forward(h, phase, feat, B);
   if (rc) return rc;
   hipLaunchKernelGGL(k_output, dim3(blocks((long long)B * O)), dim3(kT), 0, h->s, h->scratch, h->p + h->offB[6],
-                     nullptr, B, O, h->y);
+                     nullptr, nullptr, B, O, h->y);
   hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, h->s, h->y, target, (long long)B * O, h->lossd, h->dy32, h->dyb);
   CK(hipGetLastError());
   // dense output layer: dW6 = dy^T h, db6 = sum dy, dh = dy W6
@@ -1014,13 +1021,14 @@ int fft_homog_cnn_adam_step(fft_homog_cnn_t* h, float lr, float beta1, float bet
 }
 
 int fft_homog_cnn_check(fft_homog_cnn_t* h, const uint8_t* phase, const float* lam_mu, const float* feat, float* C,
-                        const float* C2, int batch, float tol, float lo, float hi, float max_spread, int* ok) {
+                        const float* C2, int batch, float tol, float lo, float hi, float max_spread, int* ok,
+                        float* spread_out) {
   if (!h || !phase || !lam_mu || !C || !ok || (h->d.n_feat > 0 && !feat)) return FFT_HOMOG_EINVAL;
   if (h->d.n_out != 21) return FFT_HOMOG_EINVAL;
   if (batch < 1) return FFT_HOMOG_EINVAL;
   const long long Nv = (long long)h->d.n * h->d.n * h->d.n;
   hipLaunchKernelGGL(k_check, dim3(batch), dim3(kT), 0, h->s, phase, Nv, lam_mu, feat, h->d.n_feat, C, C2, tol, lo, hi,
-                     max_spread, ok);
+                     max_spread, ok, spread_out);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(h->s));
   return FFT_HOMOG_OK;

@@ -3,11 +3,13 @@
 ``CNN`` marshals arguments to the C ABI (every layer, the backward pass and the
 optimizer run in the HIP library).  ``StiffnessSurrogate`` holds the data
 conventions: input = phase indicator of an n^3 cell plus log(E2/E1); output =
-the 21 upper-triangle components of the 6x6 homogenized stiffness divided by
-sqrt(mu_Voigt mu_Reuss) of the cell (linear elasticity is homogeneous of degree
-one in the moduli, and this scale keeps the targets O(1) at any contrast),
-standardised per component during training and un-standardised by folding the
-scales into the last layer afterwards.  Samples that fft_homog_cnn_check rejects go to the
+the position of the 6x6 homogenized stiffness between the cell's Reuss and
+Voigt bounds, y = (C - C_Reuss) / |C_Voigt - C_Reuss|_F on the 21 upper-triangle
+components (C lies between the bounds, so y is O(1); the prediction's error in C
+is that of y times the bounds' gap, which vanishes as the phase contrast goes to
+one), standardised per component during training and un-standardised by folding
+the scales into the last layer afterwards; the forward pass then returns
+C = C_Reuss + gap * y.  Samples that fft_homog_cnn_check rejects go to the
 FP64 solver (multi-cell tangent handles).
 """
 
@@ -48,10 +50,10 @@ def load_library():
         "fft_homog_cnn_create": (I, [D, P, S, P, ctypes.POINTER(P)]),
         "fft_homog_cnn_set_params": (I, [P, P]),
         "fft_homog_cnn_get_params": (I, [P, P]),
-        "fft_homog_cnn_forward": (I, [P, P, P, P, P, I]),
+        "fft_homog_cnn_forward": (I, [P, P, P, P, P, P, I]),
         "fft_homog_cnn_loss_grad": (I, [P, P, P, P, I, ctypes.POINTER(F), P]),
         "fft_homog_cnn_adam_step": (I, [P, F, F, F, F]),
-        "fft_homog_cnn_check": (I, [P, P, P, P, P, P, I, F, F, F, F, P]),
+        "fft_homog_cnn_check": (I, [P, P, P, P, P, P, I, F, F, F, F, P, P]),
         "fft_homog_cnn_last_ms": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "fft_homog_cnn_destroy": (None, [P]),
         "fft_homog_cnn_debug_gemm": (I, [P, I, I, I, P, LL, LL, P, LL, LL, P, I]),
@@ -139,13 +141,14 @@ class CNN:
         self._check(self.L.fft_homog_cnn_get_params(self.h, _p(out)))
         return out
 
-    def forward(self, phase, feat, out_scale=None):
+    def forward(self, phase, feat, out_scale=None, out_offset=None):
         ph = self._u8(phase)
         B = ph.shape[0]
         ft = self._f32(feat).reshape(B, self.n_feat) if self.n_feat else None
         sc = None if out_scale is None else self._f32(out_scale).reshape(B)
+        of = None if out_offset is None else self._f32(out_offset).reshape(B, self.n_out)
         out = self.torch.empty((B, self.n_out), dtype=self.torch.float32, device=self.device)
-        self._check(self.L.fft_homog_cnn_forward(self.h, _p(ph), _p(ft), _p(sc), _p(out), B))
+        self._check(self.L.fft_homog_cnn_forward(self.h, _p(ph), _p(ft), _p(sc), _p(of), _p(out), B))
         return out
 
     def loss_grad(self, phase, feat, target, want_grad=True):
@@ -161,8 +164,10 @@ class CNN:
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._check(self.L.fft_homog_cnn_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))
 
-    def check(self, phase, lam_mu, feat, C21, tol=0.0, feat_lo=-1e30, feat_hi=1e30, C2=None, max_spread=1e30):
-        """Indicator per sample; with C2, C21 (a device f32 tensor) is replaced by the ensemble mean."""
+    def check(self, phase, lam_mu, feat, C21, tol=0.0, feat_lo=-1e30, feat_hi=1e30, C2=None, max_spread=1e30,
+              want_spread=False):
+        """Indicator per sample (and, with want_spread, the members' spread per sample); with C2, C21
+        (a device f32 tensor) is replaced by the ensemble mean."""
         ph = self._u8(phase)
         B = ph.shape[0]
         lm = self._f32(lam_mu).reshape(B, 4)
@@ -171,9 +176,10 @@ class CNN:
             and C21.is_contiguous() else self._f32(C21).reshape(B, 21)
         C2t = None if C2 is None else self._f32(C2).reshape(B, 21)
         ok = self.torch.empty(B, dtype=self.torch.int32, device=self.device)
+        sp = self.torch.empty(B, dtype=self.torch.float32, device=self.device) if want_spread else None
         self._check(self.L.fft_homog_cnn_check(self.h, _p(ph), _p(lm), _p(ft), _p(C), _p(C2t), B, float(tol),
-                                               float(feat_lo), float(feat_hi), float(max_spread), _p(ok)))
-        return ok
+                                               float(feat_lo), float(feat_hi), float(max_spread), _p(ok), _p(sp)))
+        return (ok, sp) if want_spread else ok
 
     def last_ms(self):
         f, t = ctypes.c_double(0), ctypes.c_double(0)
@@ -245,6 +251,9 @@ class StiffnessSurrogate:
         self.std = np.ones(21)
         self.feat_range = (-np.inf, np.inf)
         self.folded = False
+        # indicator settings: bounds slack and members' spread limit (calibrate() sets the latter)
+        self.tol = 0.02
+        self.max_spread = 0.03
 
     @staticmethod
     def features(tables):
@@ -253,15 +262,36 @@ class StiffnessSurrogate:
         return np.log(t[:, 1, 1] / t[:, 0, 1])[:, None]
 
     @staticmethod
-    def scale(tables, fractions):
-        """Output scale of each cell: sqrt(mu_Voigt mu_Reuss), the geometric mean of the two bounds
-        of the shear modulus for stiff volume fraction f (so that targets are O(1) at any contrast)."""
+    def bounds(tables, fractions):
+        """Voigt and Reuss bounds (6x6 Voigt matrices, engineering shear) of two-phase cells with
+        isotropic phases (lam, mu) and stiff volume fraction f: arithmetic means of lam and mu, and
+        harmonic means of the bulk and shear moduli."""
         t = np.asarray(tables, dtype=np.float64)
         f = np.asarray(fractions, dtype=np.float64)
-        m0, m1 = t[:, 0, 1], t[:, 1, 1]
-        mv = (1.0 - f) * m0 + f * m1
-        mr = 1.0 / ((1.0 - f) / m0 + f / m1)
-        return np.sqrt(mv * mr)
+        f0 = 1.0 - f
+        l0, m0, l1, m1 = t[:, 0, 0], t[:, 0, 1], t[:, 1, 0], t[:, 1, 1]
+        lv, mv = f0 * l0 + f * l1, f0 * m0 + f * m1
+        k0, k1 = l0 + 2.0 * m0 / 3.0, l1 + 2.0 * m1 / 3.0
+        kr, mr = 1.0 / (f0 / k0 + f / k1), 1.0 / (f0 / m0 + f / m1)
+        lr = kr - 2.0 * mr / 3.0
+
+        def iso(lam, mu):
+            C = np.zeros(lam.shape + (6, 6))
+            C[:, :3, :3] = lam[:, None, None]
+            for i in range(3):
+                C[:, i, i] += 2.0 * mu
+                C[:, 3 + i, 3 + i] = mu
+            return C
+        return iso(lv, mv), iso(lr, mr)
+
+    @classmethod
+    def reference(cls, tables, fractions):
+        """(C_Reuss upper triangle [S, 21], |C_Voigt - C_Reuss|_F [S]) of each cell: the output offset
+        and scale of the network."""
+        CV, CR = cls.bounds(tables, fractions)
+        gap = np.linalg.norm((CV - CR).reshape(len(CV), -1), axis=1)
+        gap = np.maximum(gap, 1e-12 * np.linalg.norm(CV.reshape(len(CV), -1), axis=1))
+        return upper21(CR), gap
 
     @staticmethod
     def fractions(phase):
@@ -272,7 +302,8 @@ class StiffnessSurrogate:
         """phase: device uint8 [S, n, n, n]; tables [S, 2, 2] (lam, mu); C [S, 6, 6] solver tangents."""
         torch = self.net.torch
         feat = self.features(tables)
-        y = upper21(C) / self.scale(tables, self.fractions(phase))[:, None]
+        ref, gap = self.reference(tables, self.fractions(phase))
+        y = (upper21(C) - ref) / gap[:, None]
         self.mean = y.mean(axis=0)
         self.std = y.std(axis=0) + 1e-12
         # inputs are trusted where the training data is dense: the central 95 % of its contrasts
@@ -321,31 +352,73 @@ class StiffnessSurrogate:
             net.set_params(th.astype(np.float32))
         self.folded = True
 
-    def predict_checked(self, phase, tables, tol=0.0, max_spread=1e30):
-        """C21 (absolute units; the ensemble mean) of a batch of cells and the per-sample indicator."""
+    def predict_checked(self, phase, tables, tol=None, max_spread=None, want_spread=False):
+        """C21 (absolute units; the ensemble mean) of a batch of cells and the per-sample indicator
+        (by default with the bounds slack and the calibrated spread limit of this surrogate)."""
         self.fold()
         torch = self.net.torch
+        tol = self.tol if tol is None else tol
+        max_spread = self.max_spread if max_spread is None else max_spread
         ft = torch.as_tensor(self.features(tables).astype(np.float32), device=self.net.device)
-        sc = torch.as_tensor(self.scale(tables, self.fractions(phase)).astype(np.float32), device=self.net.device)
-        C = self.nets[0].forward(phase, ft, sc)
-        C2 = self.nets[1].forward(phase, ft, sc) if len(self.nets) > 1 else None
+        ref, gap = self.reference(tables, self.fractions(phase))
+        sc = torch.as_tensor(gap.astype(np.float32), device=self.net.device)
+        of = torch.as_tensor(ref.astype(np.float32), device=self.net.device)
+        C = self.nets[0].forward(phase, ft, sc, of)
+        C2 = self.nets[1].forward(phase, ft, sc, of) if len(self.nets) > 1 else None
         lm = torch.as_tensor(np.asarray(tables, dtype=np.float32).reshape(-1, 4), device=self.net.device)
-        ok = self.net.check(phase, lm, ft, C, tol, self.feat_range[0], self.feat_range[1], C2=C2,
-                            max_spread=max_spread)
-        return C, ok
+        res = self.net.check(phase, lm, ft, C, tol, self.feat_range[0], self.feat_range[1], C2=C2,
+                             max_spread=max_spread, want_spread=want_spread)
+        if want_spread:
+            return C, res[0], res[1]
+        return C, res
 
-    def indicator_parts(self, phase, tables, tol=0.0, max_spread=1e30):
+    def calibrate(self, phase, tables, C_true, target=0.02, safety=0.8):
+        """Set the members' spread limit from held-out cells with known tangents (cells used neither
+        for training nor for reporting): the largest limit at which every calibration cell the
+        indicator accepts has a relative Frobenius error of at most safety * target.  The other
+        tests (positive definiteness, bounds, contrast range) keep their settings.  Returns the
+        calibration statistics."""
+        assert len(self.nets) == 2, "the spread test needs two members"
+        C, ok, sp = self.predict_checked(phase, tables, max_spread=1e30, want_spread=True)
+        Cp = full6(C.cpu().numpy().astype(np.float64))
+        Ct = np.asarray(C_true, dtype=np.float64)
+        n = Ct.shape[0]
+        err = np.linalg.norm((Cp - Ct).reshape(n, -1), axis=1) / np.linalg.norm(Ct.reshape(n, -1), axis=1)
+        ok = ok.cpu().numpy().astype(bool)
+        sp = sp.cpu().numpy().astype(np.float32)
+        bound = safety * target
+        cand = np.nonzero(ok)[0]
+        order = cand[np.argsort(sp[cand], kind="stable")]
+        runmax = np.maximum.accumulate(err[order]) if order.size else np.zeros(0)
+        # the last position whose running maximum is within the bound and whose spread differs from
+        # the next one (a tie would admit the next cell too); the limit is that spread, which the
+        # kernel compares in double, so a borderline cell may only be rejected, never admitted
+        ssorted = sp[order]
+        distinct = np.append(ssorted[1:] > ssorted[:-1], True) if order.size else np.zeros(0, bool)
+        good = np.nonzero((runmax <= bound) & distinct)[0]
+        self.max_spread = float(ssorted[good[-1]]) if good.size else 0.0
+        acc = ok & (sp <= np.float32(self.max_spread))
+        return {"max_spread": self.max_spread, "target": target, "safety": safety, "cells": int(n),
+                "accepted": int(acc.sum()),
+                "accepted_max_error": float(err[acc].max()) if acc.any() else None,
+                "all_max_error": float(err.max())}
+
+    def indicator_parts(self, phase, tables, tol=None, max_spread=None):
         """Diagnostics: the indicator's three tests evaluated one at a time (bounds, spread, contrast range)."""
         self.fold()
         torch = self.net.torch
         ft = torch.as_tensor(self.features(tables).astype(np.float32), device=self.net.device)
-        sc = torch.as_tensor(self.scale(tables, self.fractions(phase)).astype(np.float32), device=self.net.device)
+        ref, gap = self.reference(tables, self.fractions(phase))
+        sc = torch.as_tensor(gap.astype(np.float32), device=self.net.device)
+        of = torch.as_tensor(ref.astype(np.float32), device=self.net.device)
         lm = torch.as_tensor(np.asarray(tables, dtype=np.float32).reshape(-1, 4), device=self.net.device)
-        outs = [net.forward(phase, ft, sc) for net in self.nets]
+        outs = [net.forward(phase, ft, sc, of) for net in self.nets]
         C2 = outs[1] if len(outs) > 1 else None
         mean = outs[0].clone() if C2 is None else 0.5 * (outs[0] + C2)
+        tol = self.tol if tol is None else tol
         bounds = self.net.check(phase, lm, ft, mean, tol).cpu().numpy()
         spread = np.ones_like(bounds)
+        max_spread = self.max_spread if max_spread is None else max_spread
         if C2 is not None:
             # a slack of 10 |C_Voigt| leaves only the positive definiteness of C and the spread
             spread = self.net.check(phase, lm, ft, outs[0].clone(), 10.0, C2=C2, max_spread=max_spread).cpu().numpy()

@@ -89,6 +89,9 @@ def test_forward_matches_oracle_small():
     scale = np.array([2.0, 0.5, 3.0], np.float32)
     ys = h.forward(phase, feat, scale).cpu().numpy()
     assert np.allclose(ys, y * scale[:, None], rtol=1e-6, atol=0)
+    offset = rng.standard_normal(y.shape).astype(np.float32)
+    yo = h.forward(phase, feat, scale, offset).cpu().numpy()
+    assert np.allclose(yo, offset + y * scale[:, None], rtol=1e-6, atol=1e-6)
 
 
 def test_gradient_matches_oracle_small():
@@ -218,3 +221,10 @@ def test_indicator_with_a_second_member_averages_and_tests_the_spread():
     # spreads 0.02 / 1.01 and 0.2 / 1.1 of the mean
     assert list(ok) == [1, 0]
     assert np.allclose(Ct.cpu().numpy(), 0.5 * (C1 + C2), rtol=1e-6)
+    # the per-sample spread the caller calibrates its limit on
+    Ct = torch.as_tensor(C1).cuda()
+    ok2, sp = h.check(phase, tables.reshape(2, 4), feat, Ct, 0.0, 0.0, 2.0, C2=C2, max_spread=0.05, want_spread=True)
+    assert list(ok2.cpu().numpy()) == [1, 0]
+    assert np.allclose(sp.cpu().numpy(), [0.02 / 1.01, 0.2 / 1.1], rtol=1e-5)
+    ok1, sp1 = h.check(phase, tables.reshape(2, 4), feat, torch.as_tensor(C1).cuda(), 0.0, 0.0, 2.0, want_spread=True)
+    assert np.all(sp1.cpu().numpy() == 0.0)

@@ -1,9 +1,11 @@
 """What the trained stiffness surrogate gains over the solver alone, at a test-sized scale.
 
 Training data: FP64 solver tangents of 16^3 cells (multi-cell handles).  After a
-short training run of the two-member ensemble on the GPU kernels, held-out
-predictions must be close to the solver's tangents, much faster to obtain, and
-the indicator must send out-of-distribution inputs back to the solver.
+short training run of the two-member ensemble on the GPU kernels, the indicator's
+spread limit is calibrated on a held-out split; on a further held-out split the
+predictions must be close to the solver's tangents, every accepted prediction
+within 2 % of it, much faster to obtain, and out-of-distribution inputs must go
+back to the solver.
 """
 
 import time
@@ -21,27 +23,30 @@ def test_surrogate_learns_solver_tangents_and_beats_its_throughput():
     from paper_2408_03804_amd.batch import TangentBatcher
     from paper_2408_03804_amd.surrogate import StiffnessSurrogate, full6
 
-    ntr, nte = 3072, 256
-    cells = workloads.workload_tangent_cells(ntr + nte, n=16, seed=1, correlation_length=4.0)
+    ntr, ncal, nte = 4096, 1024, 256
+    cells = workloads.workload_tangent_cells(ntr + ncal + nte, n=16, seed=1, correlation_length=4.0)
     phase = torch.stack([torch.as_tensor(c["phase"]) for c in cells]).cuda()
     tables = np.stack([c["table"] for c in cells])
     b = TangentBatcher(tol_cg=1e-10, max_cg=20000, autotune=False)
-    C, info = b.tangents([dict(phase=phase[i], table=tables[i]) for i in range(ntr + nte)])
+    C, info = b.tangents([dict(phase=phase[i], table=tables[i]) for i in range(ntr + ncal + nte)])
     assert all(r["status"] == "ok" for r in info)
 
-    sur = StiffnessSurrogate(n=16, max_batch=256, seed=3, members=2)
-    hist = sur.fit(phase[:ntr], tables[:ntr], C[:ntr], epochs=30, batch=128, lr=2e-3)
+    sur = StiffnessSurrogate(n=16, max_batch=1024, seed=3, members=2)
+    hist = sur.fit(phase[:ntr], tables[:ntr], C[:ntr], epochs=40, batch=128, lr=2e-3)
     for h in hist:
         assert h[-1] < 0.1 * h[0]
-    tp, tt, Ct = phase[ntr:], tables[ntr:], C[ntr:]
-    C21, ok = sur.predict_checked(tp, tt, tol=0.02, max_spread=0.05)
+    # the spread limit from a calibration split, then the report on cells used for neither
+    cal = sur.calibrate(phase[ntr:ntr + ncal], tables[ntr:ntr + ncal], C[ntr:ntr + ncal], target=0.02, safety=0.7)
+    assert cal["accepted"] > 0 and cal["accepted_max_error"] <= 0.014
+    tp, tt, Ct = phase[ntr + ncal:], tables[ntr + ncal:], C[ntr + ncal:]
+    C21, ok = sur.predict_checked(tp, tt)
     Cp = full6(C21.cpu().numpy().astype(np.float64))
     err = np.linalg.norm((Cp - Ct).reshape(nte, -1), axis=1) / np.linalg.norm(Ct.reshape(nte, -1), axis=1)
     assert np.median(err) < 0.03 and err.mean() < 0.05, (np.median(err), err.mean())
     okh = ok.cpu().numpy().astype(bool)
-    assert okh.mean() > 0.5
-    # accepted predictions are on average no worse than all predictions
-    assert err[okh].mean() <= err.mean() + 1e-12
+    # the 2 % contract: every accepted held-out prediction within 2 % (the rest go to the solver)
+    assert okh.mean() > 0.3, okh.mean()
+    assert err[okh].max() <= 0.02, (err[okh].max(), cal)
 
     # throughput: surrogate (both members + indicator) against the solver on the same cells
     test_cells = [dict(phase=tp[i], table=tt[i]) for i in range(nte)]
@@ -62,7 +67,7 @@ def test_surrogate_learns_solver_tangents_and_beats_its_throughput():
     # contrasts far outside the training range are sent back to the solver
     far = tt.copy()
     far[:, 1, :] *= 1e3
-    _, ok_far = sur.predict_checked(tp, far, tol=0.02, max_spread=0.05)
+    _, ok_far = sur.predict_checked(tp, far)
     assert ok_far.sum().item() == 0
     b.close()
     sur.close()

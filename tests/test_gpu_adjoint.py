@@ -61,7 +61,7 @@ def test_energy_gradient_is_envelope_form_without_cg():
     assert field_err(g.cpu().numpy(), 3.0 * psi / (psi.size * rho)) < 1e-14
 
 
-def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
+def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10, max_cg=20000):
     """Central differences of full solves (restarted from the converged base state) on random voxels.
 
     The energy part of J(rho + h) - J(rho - h) is summed voxel by voxel.  Away from the perturbed
@@ -80,11 +80,12 @@ def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
     value assembled from O((lam + 2 mu) |F|) terms.  The bound takes four times those sizes.
     """
     shape = w["shape"]
-    h = make(shape, "finite", "neo_hookean", tol_cg=tol_cg, tol_newton=tol_newton, max_cg=20000)
+    h = make(shape, "finite", "neo_hookean", tol_cg=tol_cg, tol_newton=tol_newton, max_cg=max_cg)
     h.set_material(w["phase"], w["table"], rho, 3.0)
     out, psi, st = h.solve(w["macro"], w["n_increments"])
     assert st["status"] == "ok"
-    g, _ = h.adjoint(ws, we)
+    g, sa = h.adjoint(ws, we)
+    assert sa["status"] == "ok"
     g = g.cpu().numpy()
     base = h.get_field(0).clone()
     N = rho.size
@@ -125,11 +126,31 @@ def _fd_check(w, rho, ws, we, nvox, seed, tol, tol_cg=1e-10, tol_newton=1e-10):
                                   + 2.0 * np.linalg.norm(ws) * rms_pterm)
         floor = noise / (2 * hstep * N)
         assert abs(fd - g[v]) <= tol * abs(g[v]) + floor, (v, fd, g[v], floor)
+    return st, sa
 
 
-# Densities down to 0.2: with rho down to 0.01 and p = 3 the stiffness spans ~2e7 and the
-# unpreconditioned CG needs ~1e5 iterations per Newton step, beyond a test's budget.
+# Densities down to 0.2 at the larger grids: with rho down to 0.01 and p = 3 the stiffness spans
+# ~2e7, and the unpreconditioned CG of the method needs ~2e4 iterations per Newton step already at
+# 16^3 (test_full_density_range_finite_differences covers that range there).
 RHO_MIN = 0.2
+
+
+def test_full_density_range_finite_differences():
+    """The SIMP range rho in [0.01, 1] of the workload (E = rho^3 E0, phase contrast 20: stiffness
+    spanning ~2e7) at 16^3, where the unpreconditioned CG is affordable: an objective with both an
+    energy and a stress part (the adjoint CG runs) against central differences of full solves on
+    20 random voxels.  CG: about 16,000-22,000 iterations per Newton step at tolerance 1e-11, near
+    the floor that rounding leaves at this conditioning (at 1e-12 some solves stagnate just above
+    the tolerance)."""
+    w = workloads.workload_neohookean3d(n=16, correlation_length=4.0)
+    w["n_increments"] = 2
+    rho = workloads.simp_density(w["shape"], 4.0, 2, rho_min=0.01)
+    assert rho.min() < 0.02 and rho.max() > 0.98
+    ws = np.zeros(9)
+    ws[0] = 1.0
+    ws[1] = 0.5
+    st, sa = _fd_check(w, rho, ws, 0.3, 20, 5, 1e-5, tol_cg=1e-11, tol_newton=1e-12, max_cg=100000)
+    assert min(st["cg"]) > 10000 and sa["cg_total"] > 10000
 
 
 def test_energy_gradient_finite_differences_128_bench_configuration():

@@ -181,9 +181,13 @@ def bench_cells(args, name, cells, description):
     for key, shp in b.shapes.items():
         log("launch shape %s: %s" % (key, shp))
     torch.cuda.synchronize()
+    # monotonic-clock bounds of the timed region (the clock of rocprofv3's kernel timestamps), so that
+    # a kernel trace of this run can be cut to it
+    mono0 = time.monotonic_ns()
     t0 = time.perf_counter()
     vox_iters = 0
     cg = 0
+    cg_group = {}
     for i in range(args.steps):
         C, info = b.tangents(dev)
         for r in info:
@@ -191,8 +195,10 @@ def bench_cells(args, name, cells, description):
                 raise RuntimeError("tangent solve failed: %s" % r)
             vox_iters += int(np.prod(r["shape"])) * r["cg_total"]
             cg += r["cg_total"]
+            cg_group[str(r["shape"])] = cg_group.get(str(r["shape"]), 0) + r["cg_total"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log("timed window monotonic ns %d %d" % (mono0, time.monotonic_ns()))
     # whole-job effective bandwidth: algorithmic bytes of every CG iteration run / wall time
     groups = {}
     for r in info:
@@ -222,6 +228,7 @@ def bench_cells(args, name, cells, description):
                    "graph": not args.no_graph, "autotune": not args.no_autotune, "concurrent": args.concurrent,
                    "launch_shapes": {str(k): v for k, v in b.shapes.items()},
                    "cg_iterations_per_step": cg // args.steps,
+                   "cg_iterations_per_step_by_group": {k: v // args.steps for k, v in cg_group.items()},
                    "voxel_iters_per_s": vox_iters / wall},
         "roofline": {"bound": "hbm", "kernel": "whole tangent job (all CG passes, effective)",
                      "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -580,8 +580,8 @@ __device__ __forceinline__ void project_small(double2* v, const double* nv) {
 // couples all C Mandel components.  LDS layout: element o of sequence (jj, s)
 // at D[o * nseq + jj * tw + s], nseq = G * tw, one FFT call for all of them.
 template <int MODE, int SMALL, int NDIM>
-// 5 waves per SIMD (at most 102 VGPRs): measured 6 % faster at 128^3 than the unconstrained 127
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) k_outer(AxisArgs a) {
+// uncapped: a 5-wave cap spilled 87 VGPRs in the small-strain projection (256-cell job 2 % slower)
+__global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
   constexpr int C = SMALL ? (NDIM == 3 ? 6 : 3) : (NDIM == 3 ? 9 : 4);
   constexpr int G = SMALL ? C : NDIM;
   constexpr int NGRP = C / G;

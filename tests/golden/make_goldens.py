@@ -7,6 +7,7 @@ taken from the HIP path.  The GPU parity tests compare against these files.
     python tests/golden/make_goldens.py spheres64   # 64^3 RSA spheres: 6x6 tangent
     python tests/golden/make_goldens.py nh64        # 64^3 Neo-Hookean GRF, 10 increments
     python tests/golden/make_goldens.py nh128       # the same at 128^3 (hours of CPU time)
+    python tests/golden/make_goldens.py uq256       # a 32^3 and a 96^3 cell of the 256-cell workload
 
 Each run writes ``<name>.json`` (homogenized values, iteration counts, settings and
 the command) and, for the Neo-Hookean solves, ``<name>_samples.npz`` with the
@@ -61,6 +62,26 @@ def spheres(n):
     return w["name"] + "_tangent", out, None
 
 
+def uq_cells():
+    """6x6 tangents of the first 32^3 and the first 96^3 cell of the 256-cell uneven-size workload."""
+    cells = workloads.workload_uq_cells(256)
+    sizes = [c["shape"][0] for c in cells]
+    out = {"workload": "uq256", "what": "6x6 homogenized tangents (Voigt, engineering shear) of single cells of the "
+           "256-cell small-strain linear elastic workload of uneven size, at the reference state, implicit "
+           "linearisation, energy form", "tol_cg": TOL_CG, "cells": []}
+    t0 = time.time()
+    for n in (32, 96):
+        i = sizes.index(n)
+        c = cells[i]
+        tab = np.asarray(c["table"])
+        prob = newton_cg.Problem(c["shape"], "linear_elastic", tab[c["phase"], 0], tab[c["phase"], 1])
+        C, Cd, counts = newton_cg.homogenized_tangent(prob, newton_cg.initial_state(prob), tol_cg=TOL_CG)
+        out["cells"].append({"index": i, "grid": list(c["shape"]), "stiff_fraction": float(c["phase"].mean()),
+                             "table": tab.tolist(), "C": C.tolist(), "cg_per_load": [int(k) for k in counts]})
+    out["oracle_seconds"] = time.time() - t0
+    return "uq256_cells", out, None
+
+
 def neohookean(n):
     w = workloads.workload_neohookean3d(n=n)
     tab = np.asarray(w["table"])
@@ -92,7 +113,7 @@ def neohookean(n):
 
 def main(argv):
     jobs = {"spheres64": lambda: spheres(64), "nh64": lambda: neohookean(64), "nh128": lambda: neohookean(128),
-            "nh16": lambda: neohookean(16)}
+            "uq256": uq_cells}
     for name in argv[1:]:
         stem, out, samples = jobs[name]()
         out["command"] = "python tests/golden/make_goldens.py " + name

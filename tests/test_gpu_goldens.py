@@ -76,3 +76,26 @@ def test_neohookean_grf_matches_oracle(n):
     F = h.get_field(0).cpu().numpy().reshape(9, -1)[:, smp["index"]].T
     Fbar = w["macro"].reshape(1, 9)
     assert field_err(F - Fbar, smp["F"] - Fbar) < TOL_FIELD
+
+
+def test_uneven_cells_tangents_under_the_jobs_autotuned_shapes():
+    """The 256-cell job of uneven size run as bench.py runs it (multi-cell handles per size group,
+    launch shapes from the autotuner, graph replay): the tangents of its first 32^3 and first 96^3
+    cell match the oracle's (tests/golden/uq256_cells.json)."""
+    import torch
+
+    from paper_2408_03804_amd.batch import TangentBatcher
+    g = load("uq256_cells")
+    cells = workloads.workload_uq_cells(256)
+    dev = [dict(phase=torch.as_tensor(c["phase"]).to("cuda:0"), table=c["table"]) for c in cells]
+    b = TangentBatcher(tol_cg=g["tol_cg"], max_cg=20000, graph=True, autotune=True, device="cuda:0")
+    C, info = b.tangents(dev)
+    assert all(r["status"] == "ok" for r in info)
+    tuned = {k[0]: v for k, v in b.shapes.items()}
+    assert (32, 32, 32) in tuned and (96, 96, 96) in tuned
+    for ref in g["cells"]:
+        i = ref["index"]
+        assert list(cells[i]["shape"]) == ref["grid"]
+        Cref = np.asarray(ref["C"])
+        assert np.abs(C[i] - Cref).max() < TOL_HOMOG * np.abs(Cref).max(), (ref["grid"], tuned[tuple(ref["grid"])])
+    b.close()

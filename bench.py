@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = ["xfwd_cgop", "reduce_pq", "y_fwd", "outer_project", "y_inv", "xinv_cgupdate", "reduce_rr"]
 
 
-CG_KERNEL_SOURCES = ["common.h", "dual.h", "fft_lds.h", "kernels.h", "kernels.hip", "launch_geometry.cpp", "materials.h"]
+CG_KERNEL_SOURCES = ["common.h", "dual.h", "fft_lds.h", "kernels.h", "kernels.hip", "launch_geometry.cpp", "materials.h",
+                     "pass_kernels.h"]
 
 
 def kernel_source_hash():

@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfft_homog.so")
-SOURCES = ["kernels.hip", "fft_homog.hip", "cnn.hip", "launch_geometry.cpp", "noalloc_scratch.hip"]
-HEADERS = ["common.h", "dual.h", "materials.h", "fft_lds.h", "kernels.h"]
+SOURCES = ["kernels.hip", "kernels_chirp.hip", "fft_homog.hip", "cnn.hip", "launch_geometry.cpp", "noalloc_scratch.hip"]
+HEADERS = ["common.h", "dual.h", "materials.h", "fft_lds.h", "kernels.h", "pass_kernels.h"]
 
 FLAGS = [
     "-O3",
@@ -30,7 +30,8 @@ FLAGS = [
 # finite values (results change at most in the sign of a zero) and removes a sixth of the
 # forward x pass's time.  They also let the compiler assume no NaN or Inf, so every domain and
 # breakdown test in those kernels is an integer test on the exponent bits (finite_bits).
-PER_FILE = {"kernels.hip": ["-ffinite-math-only", "-fno-signed-zeros"]}
+PER_FILE = {"kernels.hip": ["-ffinite-math-only", "-fno-signed-zeros"],
+            "kernels_chirp.hip": ["-ffinite-math-only", "-fno-signed-zeros"]}
 
 
 def hipcc():

@@ -49,14 +49,24 @@ __host__ __device__ inline int kx_tile_width(int nxh, int TX, int b) { return b 
 __host__ __device__ inline int kx_tile_max(int nxh, int TX) { return TX < nxh ? TX : nxh; }
 
 // Factorisation of one FFT axis into Stockham stages and its twiddle table
-// tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device memory, host-computed in
-// extended precision).
+// tw[j] = exp(-2 pi i j / L), j < L, of the transform length L the stages run on (device memory,
+// computed on the device from exact rational arguments).
+// Chirp-z axes (m > 0): a length n whose direct prime stages would cost more than the chirp-z
+// (Bluestein) form runs as a cyclic convolution of length m >= 2n - 1 (factors 2, 3 and 5): the
+// stages (nstages, radix, tw) are those of length m; chirp[j] = exp(-i pi j^2 / n), j < n, and
+// filt = FFT_m(h) / m with h_j = h_(m-j) = conj(chirp[j]) for j < n and zero between.
 struct AxisPlan {
   int n;
+  int m;         // chirp-z convolution length, 0: the stages run on n itself
   int nstages;
   int radix[kMaxStages];
   const double2* tw;
+  const double2* chirp;  // chirp-z axes only
+  const double2* filt;   // chirp-z axes only
 };
+
+// Rows per sequence that a transform of this axis occupies in LDS.
+__host__ __device__ inline int lds_len(const AxisPlan& p) { return p.m > 0 ? p.m : p.n; }
 
 // Grid geometry.  2D grids are stored with nz = 1; the "outer" axis is the
 // slowest non-trivial one (z in 3D, y in 2D) and the "mid" axis is y in 3D.
@@ -66,6 +76,7 @@ struct Geom {
   int nx, ny, nz;
   int nxh;     // nx/2 + 1 half-spectrum bins along x
   int nxp;     // row pitch of the stored half spectrum (nxh rounded up to 8 bins = 128 bytes)
+  int lx, lm, lo;  // LDS rows per sequence of the x, mid and outer transforms (lds_len of their plans)
   int n_outer, n_mid;
   long long N;   // voxels
   long long Nh;  // stored half-spectrum entries per component (nxp * ny * nz)

@@ -35,26 +35,6 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int ncomp_of(int kin, int ndim) { return kin == FFT_HOMOG_SMALL_STRAIN ? (ndim == 3 ? 6 : 3) : ndim * ndim; }
 
-// Factor n into Stockham radices: 8, 4, 2 for powers of two, then 3, 5 and any
-// remaining prime factor (direct DFT stage).
-bool factorize(int n, int* radix, int* nst) {
-  if (fixed_nstages(n) > 0) {
-    *nst = fixed_nstages(n);
-    for (int st = 0; st < *nst; ++st) radix[st] = fixed_radix(n, st);
-    return true;
-  }
-  int k = 0;
-  int m = n;
-  while (m % 8 == 0 && k < kMaxStages) { radix[k++] = 8; m /= 8; }
-  while (m % 4 == 0 && k < kMaxStages) { radix[k++] = 4; m /= 4; }
-  while (m % 2 == 0 && k < kMaxStages) { radix[k++] = 2; m /= 2; }
-  for (int p = 3; m > 1 && k < kMaxStages; p += 2) {
-    while (m % p == 0 && k < kMaxStages) { radix[k++] = p; m /= p; }
-  }
-  *nst = k;
-  return m == 1;
-}
-
 struct Layout {
   size_t F, x, r, p, spec, kst, phase, density, scale, table, hist, tw[3], partials, state, active, results, flags,
       total;
@@ -63,7 +43,28 @@ struct Layout {
   size_t n_results;
   int in_x, in_m, in_o;  // in-place (register-staged) FFT per pass
   size_t n_partials, smem_max;
+  bool chirp;  // axes with large prime factors use the chirp-z transform (else direct stages)
 };
+
+// Chirp-z thresholds (sum of the direct stages' prime lengths above 5, see make_plan), measured per
+// pass from CG-iteration kernel times on MI355X with both forms, lengths 31 to 511 in 2D and 3D:
+// the outer pass (G-hat between a forward and an inverse transform) gains from 80 (511 = 7 * 73)
+// and 97 on and loses at 61 and at 36 (299 = 13 * 23); the x passes break even at 127 and gain
+// at 199, the y pass loses at 97.  The x and y passes hold more sequences per block, which the
+// chirp-z buffers (about twice the axis length) crowd out.
+constexpr int kChirpOuter = 70;
+constexpr int kChirpRows = 150;
+
+// FFT plans of the axes of d (pl[2] = pl[1] in 2D) and the LDS lengths of g that follow from them.
+bool make_plans(const fft_homog_desc* d, bool chirp, AxisPlan* pl, Geom* g) {
+  for (int a = 0; a < 3; ++a) {
+    const int lim = !chirp ? 0 : a == d->ndim - 1 ? kChirpOuter : kChirpRows;
+    if (!make_plan(a < d->ndim ? d->n[a] : 1, &pl[a], lim)) return false;
+  }
+  if (d->ndim == 2) pl[2] = pl[1];
+  set_lds_lens(g, pl);
+  return true;
+}
 
 bool make_geom(const fft_homog_desc* d, Geom* g) {
   g->ndim = d->ndim;
@@ -73,6 +74,9 @@ bool make_geom(const fft_homog_desc* d, Geom* g) {
   g->nz = d->ndim == 3 ? d->n[2] : 1;
   g->nxh = g->nx / 2 + 1;
   g->nxp = g->nxh >= 8 ? (g->nxh + 7) / 8 * 8 : g->nxh;
+  g->lx = g->nx;  // direct stages until make_plans sets the plans' LDS lengths
+  g->lm = d->ndim == 3 ? g->ny : 1;
+  g->lo = d->ndim == 3 ? g->nz : g->ny;
   g->n_outer = d->ndim == 3 ? g->nz : g->ny;
   g->n_mid = d->ndim == 3 ? g->ny : 1;
   g->N = (long long)g->nx * g->ny * g->nz;
@@ -136,24 +140,15 @@ size_t smem_needed(const Geom& g, const AxisPlan* pl, const Layout& L) {
   return m;
 }
 
-int make_layout(const fft_homog_desc* d, Layout* L) {
-  int rc = validate_desc(d);
-  if (rc) return rc;
+int make_layout_with(const fft_homog_desc* d, Layout* L, bool chirp) {
   Geom g;
   make_geom(d, &g);
   const int C = g.c;
-  for (int a = 0; a < d->ndim; ++a) {
-    int rad[kMaxStages], ns;
-    if (!factorize(d->n[a], rad, &ns)) return FFT_HOMOG_EUNSUPPORTED;
-  }
+  AxisPlan pl[3];
+  if (!make_plans(d, chirp, pl, &g)) return FFT_HOMOG_EUNSUPPORTED;
+  L->chirp = chirp;
   L->cells = d->batch > 1 ? d->batch : 1;
   L->B = (d->flags & FFT_HOMOG_FLAG_TANGENT) ? C * L->cells : 1;
-  AxisPlan pl[3];
-  for (int a = 0; a < 3; ++a) {
-    pl[a].n = a < d->ndim ? d->n[a] : 1;
-    factorize(pl[a].n, pl[a].radix, &pl[a].nstages);
-    pl[a].tw = nullptr;
-  }
   const AxisPlan& pouter = pl[d->ndim - 1];
   const int rows = g.ny * g.nz;
   // Default tiles: as large as the LDS budget allows, but small enough that each pass still
@@ -236,7 +231,7 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   const bool j2 = d->material == FFT_HOMOG_J2_PLASTIC;
   L->table = take((size_t)L->cells * (j2 ? 4 : 2) * kMaxPhase * sizeof(double));
   L->hist = take(j2 ? (size_t)(C + 1) * g.N * sizeof(double) : 0);
-  for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? (size_t)d->n[a] * sizeof(double2) : 0);
+  for (int a = 0; a < 3; ++a) L->tw[a] = take(a < d->ndim ? plan_table_elems(pl[a]) * sizeof(double2) : 0);
   // room for one partial per row, so that any x-pass block height fits (launch-shape tuning)
   size_t np = (size_t)L->B * rows;
   np = std::max(np, (size_t)C * C * L->nblk_vox);
@@ -250,6 +245,14 @@ int make_layout(const fft_homog_desc* d, Layout* L) {
   L->flags = take(16 * sizeof(int));
   L->total = off;
   return FFT_HOMOG_OK;
+}
+
+// Chirp-z plans where they cost less; the direct stages if the chirp-z buffers do not fit LDS.
+int make_layout(const fft_homog_desc* d, Layout* L) {
+  const int rc = validate_desc(d);
+  if (rc) return rc;
+  if (make_layout_with(d, L, true) == FFT_HOMOG_OK) return FFT_HOMOG_OK;
+  return make_layout_with(d, L, false);
 }
 
 // out = G*in for `batch` packed fields: the x pass (real-to-complex), the y pass, the outer pass
@@ -769,6 +772,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   fft_homog_t* h = new fft_homog();
   h->desc = *d;
   make_geom(d, &h->g);
+  make_plans(d, L.chirp, h->plan, &h->g);
   h->L = L;
   h->matcode = 2 * d->material + (d->ndim - 2);
   h->stream = (hipStream_t)hip_stream;
@@ -826,22 +830,24 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
     e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
   }
 
-  // twiddle tables, computed in extended precision and rounded once
+  // twiddle tables of the stages' length, computed in extended precision and rounded once; the
+  // chirp-z tables of chirp-z axes on the device
   std::vector<double2> tw[3];
   for (int a = 0; a < d->ndim && e == hipSuccess; ++a) {
-    const int n = d->n[a];
+    AxisPlan& pl = h->plan[a];
+    const int n = lds_len(pl);
     tw[a].resize(n);
     for (int m = 0; m < n; ++m) {
       const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
       tw[a][m] = make_double2((double)cosl(ang), (double)-sinl(ang));
     }
     double2* dtw = (double2*)(h->ws + L.tw[a]);
-    AxisPlan& pl = h->plan[a];
-    pl.n = n;
-    factorize(n, pl.radix, &pl.nstages);
-    pl.tw = dtw;
     step = "twiddle upload";
     e = hipMemcpyAsync(dtw, tw[a].data(), n * sizeof(double2), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+      step = "chirp-z tables";
+      e = launch_plan_tables(&pl, dtw, h->stream, false);
+    }
   }
   if (h->g.ndim == 2) h->plan[2] = h->plan[1];
   std::vector<double> zeros((size_t)L.cells * (j2 ? 4 : 2) * kMaxPhase, 0.0);
@@ -1538,12 +1544,14 @@ int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double*
   if (rc) return create_fail(rc, "invalid or unsupported descriptor", hipSuccess);
   Geom g;
   make_geom(d, &g);
-  // scratch: twiddle tables of the axes, then the half spectrum [batch][c][z][y][pitch]
+  AxisPlan pl[3];
+  make_plans(d, L.chirp, pl, &g);
+  // scratch: FFT tables of the axes, then the half spectrum [batch][c][z][y][pitch]
   size_t off = 0;
   size_t tw_off[3] = {0, 0, 0};
   for (int a = 0; a < d->ndim; ++a) {
     tw_off[a] = off;
-    off = align_up(off + (size_t)d->n[a] * sizeof(double2));
+    off = align_up(off + plan_table_elems(pl[a]) * sizeof(double2));
   }
   const size_t spec_off = off;
   const size_t need = spec_off + (size_t)batch * g.c * g.Nh * sizeof(double2);
@@ -1557,13 +1565,7 @@ int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double*
   hipError_t e = noalloc_scratch_address((void**)&base);
   if (e != hipSuccess) return create_fail(FFT_HOMOG_EDEVICE, "hipGetSymbolAddress(scratch)", e);
   const hipStream_t s = (hipStream_t)hip_stream;
-  AxisPlan pl[3];
-  for (int a = 0; a < 3; ++a) {
-    pl[a].n = a < d->ndim ? d->n[a] : 1;
-    factorize(pl[a].n, pl[a].radix, &pl[a].nstages);
-    pl[a].tw = a < d->ndim ? (const double2*)(base + tw_off[a]) : nullptr;
-    if (a < d->ndim && e == hipSuccess) e = launch_twiddles((double2*)(base + tw_off[a]), d->n[a], s);
-  }
+  for (int a = 0; a < d->ndim && e == hipSuccess; ++a) e = launch_plan_tables(&pl[a], (double2*)(base + tw_off[a]), s, true);
   if (d->ndim == 2) pl[2] = pl[1];
   const int matcode = 2 * d->material + (d->ndim - 2);
   if (e == hipSuccess) e = set_smem_limits(g, matcode, L.smem_max);

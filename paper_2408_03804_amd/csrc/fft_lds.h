@@ -1,5 +1,6 @@
 // Batched complex FFT of many short sequences held in LDS (Stockham autosort,
-// mixed radix 2/3/4/5/8 plus a direct DFT for any other prime factor).
+// mixed radix 2/3/4/5/8/16 plus a direct DFT for any other prime factor, or the
+// chirp-z form for lengths whose prime factors make the direct stages costly).
 //
 // Layout: `nseq` sequences of length n interleaved element-major, element i of
 // sequence s at buf[i * nseq + s].  Consecutive threads work on consecutive
@@ -211,24 +212,24 @@ __device__ __forceinline__ void stage_generic(const double2* __restrict__ src, d
   }
 }
 
-// Full transform of `nseq` interleaved sequences; returns the buffer holding the
-// result (a or b).  Must be called by every thread of the block.
+// Full transform of `nseq` interleaved sequences of length L with the stages (nst, radix, tw);
+// returns the buffer holding the result (a or b).  Must be called by every thread of the block.
 template <int DIR>
-__device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl) {
-  const int n = pl.n;
+__device__ double2* fft_stages_pp(double2* a, double2* b, int nseq, int L, int nst, const int* radix,
+                                  const double2* tw) {
   double2* src = a;
   double2* dst = b;
   int Ns = 1;
-  for (int st = 0; st < pl.nstages; ++st) {
-    const int R = pl.radix[st];
+  for (int st = 0; st < nst; ++st) {
+    const int R = radix[st];
     switch (R) {
-      case 2: stage_small<2, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      case 3: stage_small<3, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      case 4: stage_small<4, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      case 5: stage_small<5, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      case 8: stage_small<8, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      case 16: stage_small<16, DIR>(src, dst, nseq, n, Ns, pl.tw); break;
-      default: stage_generic<DIR>(src, dst, nseq, n, Ns, R, pl.tw); break;
+      case 2: stage_small<2, DIR>(src, dst, nseq, L, Ns, tw); break;
+      case 3: stage_small<3, DIR>(src, dst, nseq, L, Ns, tw); break;
+      case 4: stage_small<4, DIR>(src, dst, nseq, L, Ns, tw); break;
+      case 5: stage_small<5, DIR>(src, dst, nseq, L, Ns, tw); break;
+      case 8: stage_small<8, DIR>(src, dst, nseq, L, Ns, tw); break;
+      case 16: stage_small<16, DIR>(src, dst, nseq, L, Ns, tw); break;
+      default: stage_generic<DIR>(src, dst, nseq, L, Ns, R, tw); break;
     }
     __syncthreads();
     double2* t = src;
@@ -237,6 +238,11 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
     Ns *= R;
   }
   return src;
+}
+
+template <int DIR>
+__device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl) {
+  return fft_stages_pp<DIR>(a, b, nseq, pl.n, pl.nstages, pl.radix, pl.tw);
 }
 
 // ---- in-place variant: register-staged stages, one LDS buffer ---------------
@@ -356,36 +362,40 @@ __host__ __device__ inline bool fixed_one_ok(int n, int nseq) {
 }
 
 template <int DIR>
-__device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
+__device__ void fft_stages_ip(double2* buf, int nseq, int L, int nst, const int* radix, const double2* tw) {
   const FastDiv fd = make_fastdiv((unsigned)nseq);
-  switch (pl.n) {
-    case 256: fixed_stages<256, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 192: fixed_stages<192, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 160: fixed_stages<160, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 128: fixed_stages<128, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 96: fixed_stages<96, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 80: fixed_stages<80, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 64: fixed_stages<64, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 48: fixed_stages<48, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 32: fixed_stages<32, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 16: fixed_stages<16, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
-    case 8: fixed_stages<8, DIR, 0, 1>(buf, nseq, fd, pl.tw); return;
+  switch (L) {
+    case 256: fixed_stages<256, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 192: fixed_stages<192, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 160: fixed_stages<160, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 128: fixed_stages<128, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 96: fixed_stages<96, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 80: fixed_stages<80, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 64: fixed_stages<64, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 48: fixed_stages<48, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 32: fixed_stages<32, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 16: fixed_stages<16, DIR, 0, 1>(buf, nseq, fd, tw); return;
+    case 8: fixed_stages<8, DIR, 0, 1>(buf, nseq, fd, tw); return;
     default: break;
   }
-  const int n = pl.n;
   int Ns = 1;
-  for (int st = 0; st < pl.nstages; ++st) {
-    const int R = pl.radix[st];
+  for (int st = 0; st < nst; ++st) {
+    const int R = radix[st];
     switch (R) {
-      case 2: stage_inplace<2, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
-      case 3: stage_inplace<3, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
-      case 4: stage_inplace<4, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
-      case 5: stage_inplace<5, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
-      case 16: stage_inplace<16, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
-      default: stage_inplace<8, DIR>(buf, nseq, fd, n, Ns, pl.tw); break;
+      case 2: stage_inplace<2, DIR>(buf, nseq, fd, L, Ns, tw); break;
+      case 3: stage_inplace<3, DIR>(buf, nseq, fd, L, Ns, tw); break;
+      case 4: stage_inplace<4, DIR>(buf, nseq, fd, L, Ns, tw); break;
+      case 5: stage_inplace<5, DIR>(buf, nseq, fd, L, Ns, tw); break;
+      case 16: stage_inplace<16, DIR>(buf, nseq, fd, L, Ns, tw); break;
+      default: stage_inplace<8, DIR>(buf, nseq, fd, L, Ns, tw); break;
     }
     Ns *= R;
   }
+}
+
+template <int DIR>
+__device__ void fft_lds_inplace(double2* buf, int nseq, const AxisPlan& pl) {
+  fft_stages_ip<DIR>(buf, nseq, pl.n, pl.nstages, pl.radix, pl.tw);
 }
 
 // Transform in place when the plan allows it (inplace != 0), else ping-pong
@@ -402,6 +412,55 @@ __device__ __forceinline__ void fft_lds_any(double2* buf, double2* pong, int nse
       __syncthreads();
     }
   }
+}
+
+// ---- chirp-z (Bluestein) transform for axes with large prime factors ----------
+// With c_j = exp(DIR i pi j^2 / n) (pl.chirp for DIR = -1, its conjugate for DIR = +1),
+// j k = (j^2 + k^2 - (k - j)^2) / 2 turns the length-n DFT into
+//   X_k = c_k sum_j (x_j c_j) conj(c_(k-j)),
+// a linear convolution with the even sequence conj(c_j), |j| < n.  Zero-padded to m >= 2n - 1
+// it is a cyclic convolution of length m: a forward length-m FFT, a product with the filter
+// f = FFT_m(h) / m (pl.filt; h is even, so the DIR = +1 filter is conj(f)), an inverse length-m
+// FFT.  The LDS buffer holds m rows per sequence; the result is left in rows 0..n-1.  The
+// length-m stages run in place when the host allowed it (inplace), else through `pong`.
+// one length-m transform of the chirp-z convolution, result in buf
+template <int D>
+__device__ __forceinline__ void chirp_conv_fft(double2* buf, double2* pong, int nseq, const AxisPlan& pl, int inplace) {
+  if (inplace) {
+    fft_stages_ip<D>(buf, nseq, pl.m, pl.nstages, pl.radix, pl.tw);
+  } else {
+    double2* res = fft_stages_pp<D>(buf, pong, nseq, pl.m, pl.nstages, pl.radix, pl.tw);
+    if (res != buf) {
+      for (int t = threadIdx.x; t < pl.m * nseq; t += blockDim.x) buf[t] = res[t];
+      __syncthreads();
+    }
+  }
+}
+
+template <int DIR>
+__device__ void fft_chirp(double2* buf, double2* pong, int nseq, const AxisPlan& pl, int inplace) {
+  const int n = pl.n;
+  const int m = pl.m;
+  const FastDiv fd = make_fastdiv((unsigned)nseq);
+  for (int t = threadIdx.x; t < m * nseq; t += blockDim.x) {
+    const int j = (int)fdiv((unsigned)t, fd);
+    double2 v = make_double2(0.0, 0.0);
+    if (j < n) v = cmul(buf[t], twiddle<DIR>(pl.chirp, j));
+    buf[t] = v;
+  }
+  __syncthreads();
+  chirp_conv_fft<-1>(buf, pong, nseq, pl, inplace);
+  for (int t = threadIdx.x; t < m * nseq; t += blockDim.x) {
+    const int j = (int)fdiv((unsigned)t, fd);
+    buf[t] = cmul(buf[t], twiddle<DIR>(pl.filt, j));
+  }
+  __syncthreads();
+  chirp_conv_fft<1>(buf, pong, nseq, pl, inplace);
+  for (int t = threadIdx.x; t < n * nseq; t += blockDim.x) {
+    const int j = (int)fdiv((unsigned)t, fd);
+    buf[t] = cmul(buf[t], twiddle<DIR>(pl.chirp, j));
+  }
+  __syncthreads();
 }
 
 // ---- deterministic block reduction (wave64 shuffles, fixed order) ------------

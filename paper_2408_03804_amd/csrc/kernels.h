@@ -93,6 +93,21 @@ inline bool finite_rows(const Geom& g) { return !g.small && g.ndim == 3; }
 // true if an in-place transform of nseq sequences of this plan fits the register staging
 bool inplace_ok(const AxisPlan& pl, int nseq);
 
+// FFT plan of an axis of length n: the direct stages, or the chirp-z form with its convolution
+// length when the direct stages' prime lengths other than 2, 3 and 5 sum to more than chirp_above
+// (0: never); table pointers left null.  False if n has no factorisation within kMaxStages stages.
+bool make_plan(int n, AxisPlan* pl, int chirp_above);
+// LDS rows per sequence of the x, mid and outer transforms of the plans pl[0..ndim-1]
+void set_lds_lens(Geom* g, const AxisPlan* pl);
+// the stages of length n (radices 16/8/4/2/3/5 and remaining primes); false if more than kMaxStages
+bool factorize(int n, int* radix, int* nst);
+// complex entries of an axis plan's device tables: twiddles of lds_len, then chirp (n) and filter (m)
+size_t plan_table_elems(const AxisPlan& pl);
+// set the table pointers of pl into `base` (plan_table_elems entries, device memory) and fill the
+// tables: the twiddles (exp(-2 pi i j / L) by sincospi of exact rational arguments) unless the
+// caller wrote them there, the chirp-z tables of a chirp-z plan
+hipError_t launch_plan_tables(AxisPlan* pl, double2* base, hipStream_t s, bool twiddles);
+
 hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s);
 hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s);
@@ -119,8 +134,6 @@ hipError_t launch_expand(const double* packed, double* full, const Geom& g, hipS
 hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStream_t s);
 hipError_t launch_stress_field(int mat, const double* F, MatParams m, double* full_out, double* energy_out,
                                const Geom& g, hipStream_t s);
-// twiddle table tw[m] = exp(-2 pi i m / n), m < n, computed on the device
-hipError_t launch_twiddles(double2* tw, int n, hipStream_t s);
 hipError_t launch_simp_scale(const double* density, double p, double* scale, long long N, hipStream_t s);
 hipError_t launch_check_phase(const uint8_t* phase, long long N, int nphase, int* flag, hipStream_t s);
 hipError_t launch_debug_constitutive(int mat, const double* e, const double* de, double* P, double* KdE,
@@ -134,6 +147,12 @@ hipError_t launch_simp_gradient(int mat, const double* F, const double* x, MatPa
 hipError_t launch_j2_commit(int mat, const double* F, MatParams m, double* hist, const Geom& g, hipStream_t s);
 hipError_t launch_j2_plastic(int mat, const double* F, MatParams m, double* out, const Geom& g, hipStream_t s);
 hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes);
+// the pass kernels with the chirp-z transform (kernels_chirp.hip), for plans with m > 0
+hipError_t launch_xfwd_chirp(int prod, int mat, const XFwdArgs& a, dim3 grid, size_t sm, hipStream_t s);
+hipError_t launch_xinv_chirp(int cons, const XInvArgs& a, dim3 grid, size_t sm, hipStream_t s);
+hipError_t launch_mid_chirp(int dir, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s);
+hipError_t launch_outer_chirp(int mode, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s);
+hipError_t set_smem_limits_chirp(const Geom& g, int mat, size_t bytes);
 
 // Scratch of the allocation-free projection: a file-scope device array of this many bytes per
 // device (noalloc_scratch.hip); its address on the current device.

@@ -23,7 +23,7 @@ hipError_t launch_expand(const double*, double*, const Geom&, hipStream_t) { ret
 hipError_t launch_pack(const double*, double*, const Geom&, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_stress_field(int, const double*, MatParams, double*, double*, const Geom&, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_simp_scale(const double*, double, double*, long long, hipStream_t) { return hipErrorNoBinaryForGpu; }
-hipError_t launch_twiddles(double2*, int, hipStream_t) { return hipErrorNoBinaryForGpu; }
+hipError_t launch_plan_tables(AxisPlan*, double2*, hipStream_t, bool) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_check_phase(const uint8_t*, long long, int, int*, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_debug_constitutive(int, const double*, const double*, double*, double*, double*, MatParams, const Geom&, hipStream_t) { return hipErrorNoBinaryForGpu; }
 hipError_t launch_simp_gradient(int, const double*, const double*, MatParams, const double*, double, const double*, double, double*, const Geom&, hipStream_t) { return hipErrorNoBinaryForGpu; }

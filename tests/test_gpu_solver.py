@@ -102,6 +102,20 @@ def test_stvk_3d_ragged():
     assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
 
 
+@pytest.mark.parametrize("shape", [(6, 5, 97), (4, 199, 3), (199, 5, 4)])
+def test_neohookean_3d_chirp_z_axes(shape):
+    """Grids with a 97-point outer axis, a 199-point y axis or a 199-point x axis (chirp-z
+    transforms in the outer, y and x passes): Newton-CG solve, fields and homogenized stress
+    against the oracle."""
+    phase = workloads.random_phases(shape, 2, 11)
+    table = [[2.0, 1.0], [10.0, 5.0]]
+    F = np.array([[1.03, 0.01, 0.0], [0.0, 0.99, 0.02], [0.01, 0.0, 1.0]])
+    o = run_both(shape, "finite", "neo_hookean", phase, table, F.reshape(-1), 2)
+    check_counts(o["st"], o["ref"]["stats"])
+    assert o["field_err"] < TOL_FIELD and o["stress_err"] < TOL_FIELD
+    assert rel(o["S"], o["ref"]["macro_stress"]) < TOL_HOMOG
+
+
 def test_spheres_3d_tangent_batched():
     """RSA spheres (contrast 100) at 20^3: 6 x 6 tangent from 6 batched load cases."""
     n = 20

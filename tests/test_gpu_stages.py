@@ -21,8 +21,9 @@ FFT_SHAPES = [(7, 5), (31, 31), (8, 12), (1, 9), (6, 10, 12), (9, 16, 15), (5, 6
               (2, 4, 128), (128, 3, 2), (3, 256, 2), (16, 32, 64), (64, 16, 32), (256, 6), (5, 256),
               (2, 4, 96), (96, 3, 2), (3, 48, 2), (48, 96, 4), (48, 5),
               (2, 3, 80), (80, 4), (3, 160, 2), (160, 2, 3), (2, 192, 3), (192, 5),
-              # long prime stages (direct DFT of length 199 / 257, and 299 = 13 * 23) on each axis
-              (199, 6), (3, 257), (4, 199, 5), (299, 4), (2, 3, 199)]
+              # lengths with large prime factors on each axis: chirp-z transforms (199, 257 and, on the
+              # outer axis, 97) and direct prime stages (299 = 13 * 23, and 97 on the x axis)
+              (199, 6), (3, 257), (4, 199, 5), (299, 4), (2, 3, 199), (3, 97), (97, 3), (2, 5, 97), (4, 3, 257)]
 
 
 def make(shape, kin, mat, nphase=2, **kw):
@@ -75,7 +76,10 @@ def test_rfft_and_irfft_match_numpy(shape):
 @pytest.mark.parametrize("kin,mat", [("small", "linear_elastic"), ("finite", "neo_hookean")])
 @pytest.mark.parametrize("shape,lengths", [((7, 9), (1.0, 1.3)), ((31, 31), None), ((6, 8), None),
                                            ((5, 6, 7), (1.0, 0.8, 1.2)), ((8, 12, 10), None), ((9, 16, 15), None),
-                                           ((128, 4, 6), None), ((6, 128, 32), None)])
+                                           ((128, 4, 6), None), ((6, 128, 32), None),
+                                           # chirp-z transforms on the x, y and outer axes
+                                           ((199, 3, 4), None), ((4, 199, 3), None), ((5, 4, 97), (1.0, 0.9, 1.1)),
+                                           ((199, 8), None), ((6, 257), None)])
 def test_projection_matches_oracle(kin, mat, shape, lengths):
     d = len(shape)
     h = make(shape, kin, mat, lengths=lengths)
@@ -90,7 +94,7 @@ def test_projection_matches_oracle(kin, mat, shape, lengths):
 
 
 @pytest.mark.parametrize("mat,kin", MATS)
-@pytest.mark.parametrize("shape", [(9, 8), (6, 5, 7)])
+@pytest.mark.parametrize("shape", [(9, 8), (6, 5, 7), (199, 5), (3, 4, 97)])  # the last two: chirp-z axes
 @pytest.mark.parametrize("k_mode", [0, 1])
 def test_cg_operator_matches_oracle(mat, kin, shape, k_mode):
     d = len(shape)

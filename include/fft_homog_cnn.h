@@ -36,7 +36,7 @@ typedef struct fft_homog_cnn_desc {
   int hidden;       /* width of the hidden MLP layer (1..4096) */
   int n_feat;       /* scalar features per sample appended to the pooled features (0..32) */
   int n_out;        /* outputs per sample (1..4096) */
-  int max_batch;    /* most samples per call (>= 1) */
+  int max_batch;    /* most samples per call (>= 1, max_batch (n/2)^3 < 2^31) */
 } fft_homog_cnn_desc;
 
 typedef struct fft_homog_cnn fft_homog_cnn_t;

@@ -4,6 +4,8 @@
 //   conv forward      pre[m][co]   = col[m][k] . W[co][k]            (col = periodic stride-2 im2col)
 //   conv weight grad  dW[co][k]    = sum_m dpre[m][co] col[m][k]      (split over m, fixed-order sum)
 //   conv input grad   dcol[m][k]   = sum_co dpre[m][co] W[co][k], then a gather back to the voxels
+// col is never stored for blocks 2-4: their GEMM tile loaders gather it from the previous
+// block's activations (implicit GEMM); block 1 (one input channel, the u8 phase map) expands it.
 //   dense layers      the same three products with m = sample
 // around small element-wise kernels (bias + gelu, pooling, loss, Adam).  All sums that
 // cross blocks go through partial buffers reduced in a fixed order, so a training step is
@@ -47,6 +49,15 @@ __device__ inline float gelu_grad(float x) {
 // ---------------------------------------------------------------------------
 // GEMM: C[z][m][n] = sum_{k in split z} A(m,k) B(n,k)
 // ---------------------------------------------------------------------------
+// Implicit im2col operand of a conv block: element (row, k) of col, row = ((b m + oz) m + oy) m + ox
+// over the m^3 outputs of each sample, k = t Ci + ci with tap t = 9 tz + 3 ty + tx < 27, is
+// src[b, (2 oz + tz - 1) mod n, (2 oy + ty - 1) mod n, (2 ox + tx - 1) mod n, ci]  (n = 2 m), and
+// zero for k >= 27 Ci.  Ci % 8 == 0, so 8 consecutive k share a tap (one 16-byte load).
+struct ConvOperand {
+  const bf16* src;  // [b][z][y][x][Ci] activations of the previous block
+  int n, m, Ci;
+};
+
 struct GemmArgs {
   int M, N, K, kchunk;
   const bf16* A;
@@ -54,7 +65,41 @@ struct GemmArgs {
   const bf16* B;
   long long sbn, sbk;
   float* C;
+  ConvOperand cv;  // the implicit operand (A for CONV = 1, B for CONV = 2)
 };
+
+// periodic input coordinate of output coordinate o and tap component t (0..2)
+__device__ inline int tap_coord(int o, int t, int n) {
+  int i = 2 * o + t - 1;
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  return i;
+}
+
+// The 8 col entries (row, k..k+7) of the implicit operand (zero past 27 Ci); (b, oz, oy, ox) is row.
+__device__ inline uint4 conv_gather(const ConvOperand& c, long long b, int oz, int oy, int ox, int k) {
+  const int tap = k / c.Ci;
+  if (tap >= 27) return make_uint4(0u, 0u, 0u, 0u);
+  const int ci = k - tap * c.Ci;
+  const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+  const long long vox = ((b * c.n + tap_coord(oz, tz, c.n)) * c.n + tap_coord(oy, ty, c.n)) * c.n + tap_coord(ox, tx, c.n);
+  return *reinterpret_cast<const uint4*>(c.src + vox * c.Ci + ci);
+}
+
+// output row -> (sample, oz, oy, ox); rows are below 2^31 (max_batch m^3 outputs per block)
+__device__ inline void conv_row(const ConvOperand& c, int row, long long* b, int* oz, int* oy, int* ox) {
+  const unsigned m = (unsigned)c.m;
+  unsigned r = (unsigned)row;
+  unsigned q = r / m;
+  *ox = (int)(r - q * m);
+  r = q;
+  q = r / m;
+  *oy = (int)(r - q * m);
+  r = q;
+  q = r / m;
+  *oz = (int)(r - q * m);
+  *b = q;
+}
 
 // Stage a 64 x 32 (rows x k) operand tile into LDS, zero outside [0,nrows) x [k0,kend).
 // KC: the operand is contiguous along k (else along rows).
@@ -101,7 +146,9 @@ __device__ inline void load_tile(bf16 (*T)[LDT], const bf16* P, long long s_row,
 // gfx950 MFMA 16x16x32 bf16 (v_mfma_f32_16x16x32_bf16, one instruction per 32-deep k step of a tile):
 // lane l holds rows/cols (l mod 16) at k = 8 (l / 16) + 0..7 (one 16-byte LDS read per operand);
 // the accumulator holds column (l mod 16), rows 4 (l / 16) + 0..3.
-template <bool AK, bool BK_>
+// CONV = 1: A is the implicit im2col operand g.cv (rows = outputs, contiguous along k);
+// CONV = 2: B is (B rows = col k, GEMM k = outputs).  The other operand is read from memory.
+template <bool AK, bool BK_, int CONV = 0>
 __global__ void __launch_bounds__(kT) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) bf16 As[BM][LDT];
   __shared__ __attribute__((aligned(16))) bf16 Bs[BN][LDT];
@@ -121,9 +168,38 @@ __global__ void __launch_bounds__(kT) k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  // CONV = 1: this thread's A row of every k tile (row r = t / 4, k offset 8 (t mod 4))
+  long long cb = 0;
+  int coz = 0, coy = 0, cox = 0;
+  const int crow = m0 + (threadIdx.x >> 2);
+  if (CONV == 1 && crow < g.M) conv_row(g.cv, crow, &cb, &coz, &coy, &cox);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    load_tile<AK>(As, g.A, g.sam, g.sak, m0, g.M, k0, kend);
-    load_tile<BK_>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, kend);
+    if constexpr (CONV == 1) {
+      const int kk = (threadIdx.x & 3) * 8;
+      uint4 q = make_uint4(0u, 0u, 0u, 0u);
+      if (crow < g.M && k0 + kk < kend) q = conv_gather(g.cv, cb, coz, coy, cox, k0 + kk);
+      *reinterpret_cast<uint4*>(&As[threadIdx.x >> 2][kk]) = q;
+    } else {
+      load_tile<AK>(As, g.A, g.sam, g.sak, m0, g.M, k0, kend);
+    }
+    if constexpr (CONV == 2) {
+      // GEMM k = output row k0 + t / 8, B rows (col k) n0 + 8 (t mod 8) .. + 7, stored transposed
+      const int kk = threadIdx.x >> 3;
+      const int rr = (threadIdx.x & 7) * 8;
+      uint4 q = make_uint4(0u, 0u, 0u, 0u);
+      if (k0 + kk < kend && n0 + rr < g.N) {
+        long long b;
+        int oz, oy, ox;
+        conv_row(g.cv, k0 + kk, &b, &oz, &oy, &ox);
+        q = conv_gather(g.cv, b, oz, oy, ox, n0 + rr);
+      }
+      bf16 v[8];
+      memcpy(v, &q, 16);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[rr + i][kk] = v[i];
+    } else {
+      load_tile<BK_>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, kend);
+    }
     __syncthreads();
     static_assert(BK == 32, "one 16x16x32 MFMA per k tile");
     {
@@ -178,6 +254,45 @@ hipError_t gemm(int M, int N, int K, const bf16* A, long long sam, long long sak
   else if (ak) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(kT), 0, s, g);
   else if (bk) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(kT), 0, s, g);
   else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(kT), 0, s, g);
+  return hipGetLastError();
+}
+
+// The two conv products with the implicit im2col operand cv (Kp = 32-padded 27 Ci):
+//   forward      pre[M][N] = col[M][Kp] . W[N][Kp]                    (CONV = 1)
+//   weight grad  dW[z][co][Kp] = sum_{m in split z} dpre[m][co] col[m][Kp]   (CONV = 2; A = dpre, [M][co])
+hipError_t gemm_conv_forward(int M, int N, int Kp, const ConvOperand& cv, const bf16* W, float* C, hipStream_t s) {
+  if (M <= 0 || N <= 0 || Kp <= 0) return hipSuccess;
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = Kp;
+  g.kchunk = Kp;
+  g.B = W;
+  g.sbn = Kp;
+  g.sbk = 1;
+  g.C = C;
+  g.cv = cv;
+  hipLaunchKernelGGL((k_gemm<true, true, 1>), dim3((M + BM - 1) / BM, (N + BN - 1) / BN, 1), dim3(kT), 0, s, g);
+  return hipGetLastError();
+}
+hipError_t gemm_conv_wgrad(int Co, int Kp, int M, const bf16* dpre, const ConvOperand& cv, float* C, int splits,
+                           hipStream_t s) {
+  if (M <= 0 || Co <= 0 || Kp <= 0) return hipSuccess;
+  GemmArgs g{};
+  g.M = Co;
+  g.N = Kp;
+  g.K = M;
+  splits = std::max(1, std::min(splits, kMaxSplits));
+  int chunk = (M + splits - 1) / splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  splits = (M + chunk - 1) / chunk;
+  g.kchunk = chunk;
+  g.A = dpre;
+  g.sam = 1;
+  g.sak = Co;
+  g.C = C;
+  g.cv = cv;
+  hipLaunchKernelGGL((k_gemm<false, false, 2>), dim3((Co + BM - 1) / BM, (Kp + BN - 1) / BN, splits), dim3(kT), 0, s, g);
   return hipGetLastError();
 }
 
@@ -643,6 +758,9 @@ int validate(const fft_homog_cnn_desc* d) {
   if (d->hidden < 1 || d->hidden > 4096 || d->n_feat < 0 || d->n_feat > 32 || d->n_out < 1 || d->n_out > 4096)
     return FFT_HOMOG_EINVAL;
   if (d->max_batch < 1) return FFT_HOMOG_EINVAL;
+  // GEMM rows (outputs of block 1 over the batch) are 32-bit
+  const long long m1 = d->n / 2;
+  if ((long long)d->max_batch * m1 * m1 * m1 > 0x7fffffffLL) return FFT_HOMOG_EINVAL;
   return FFT_HOMOG_OK;
 }
 
@@ -699,7 +817,10 @@ void plan(const fft_homog_cnn_desc* d, Plan* L) {
   size_t maxact = 0, maxcol = 0;
   for (int l = 1; l <= 4; ++l) {
     const long long Ml = Bm * (long long)L->edge[l] * L->edge[l] * L->edge[l];
-    L->o_col[l] = take((size_t)Ml * L->Kp[l] * 2);
+    // block 1 always expands its operand; blocks 2-4 only when their input channels are not a
+    // multiple of 8 (else the GEMMs gather it, implicit_conv)
+    const bool expand = l == 1 || ch[l - 1] % 8 != 0;
+    L->o_col[l] = take(expand ? (size_t)Ml * L->Kp[l] * 2 : 0);
     L->o_pre[l] = take((size_t)Ml * ch[l] * 4);
     L->o_act[l] = take((size_t)Ml * ch[l] * 2);
     maxact = std::max(maxact, (size_t)Ml * ch[l]);
@@ -753,6 +874,13 @@ hipError_t colsum(fft_homog_cnn_t* h, const float* X, long long M, int C, float*
 
 int check_batch(fft_homog_cnn_t* h, int B) { return (B >= 1 && B <= h->d.max_batch) ? FFT_HOMOG_OK : FFT_HOMOG_EINVAL; }
 
+// conv block l > 1 gathers its im2col operand inside the GEMM when its input channels allow
+// 16-byte loads of 8 channels
+bool implicit_conv(const fft_homog_cnn_t* h, int l) { return l > 1 && h->d.channels[l - 1] % 8 == 0; }
+ConvOperand conv_operand(const fft_homog_cnn_t* h, int l) {
+  return ConvOperand{h->act[l - 1], h->edge[l - 1], h->edge[l], h->d.channels[l - 1]};
+}
+
 // forward pass of B samples into h->y (before output scaling is applied by the caller path)
 int forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat, int B) {
   const int* ch = h->d.channels;
@@ -760,13 +888,17 @@ int forward(fft_homog_cnn_t* h, const uint8_t* phase, const float* feat, int B) 
   for (int l = 1; l <= 4; ++l) {
     const int n = h->edge[l - 1];
     const long long Ml = (long long)B * h->edge[l] * h->edge[l] * h->edge[l];
-    if (l == 1)
-      hipLaunchKernelGGL(k_im2col_phase, dim3(blocks(Ml)), dim3(kT), 0, h->s, phase, B, n, h->Kp[1], h->col[1], h->flag);
-    else
-      hipLaunchKernelGGL(k_im2col, dim3(blocks(Ml * 27)), dim3(kT), 0, h->s, h->act[l - 1], B, n, ch[l - 1], h->Kp[l],
-                         h->col[l]);
-    CK(hipGetLastError());
-    CK(gemm((int)Ml, ch[l], h->Kp[l], h->col[l], h->Kp[l], 1, h->Wb[l], h->Kp[l], 1, h->pre[l], 1, h->s));
+    if (l == 1 || !implicit_conv(h, l)) {
+      if (l == 1)
+        hipLaunchKernelGGL(k_im2col_phase, dim3(blocks(Ml)), dim3(kT), 0, h->s, phase, B, n, h->Kp[1], h->col[1], h->flag);
+      else
+        hipLaunchKernelGGL(k_im2col, dim3(blocks(Ml * 27)), dim3(kT), 0, h->s, h->act[l - 1], B, n, ch[l - 1], h->Kp[l],
+                           h->col[l]);
+      CK(hipGetLastError());
+      CK(gemm((int)Ml, ch[l], h->Kp[l], h->col[l], h->Kp[l], 1, h->Wb[l], h->Kp[l], 1, h->pre[l], 1, h->s));
+    } else {
+      CK(gemm_conv_forward((int)Ml, ch[l], h->Kp[l], conv_operand(h, l), h->Wb[l], h->pre[l], h->s));
+    }
     hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(Ml * ch[l])), dim3(kT), 0, h->s, h->pre[l], h->p + h->offB[l], Ml, ch[l],
                        h->act[l]);
     CK(hipGetLastError());
@@ -973,7 +1105,10 @@ int fft_homog_cnn_loss_grad(fft_homog_cnn_t* h, const uint8_t* phase, const floa
   for (int l = 4; l >= 1; --l) {
     const long long Ml = (long long)B * h->edge[l] * h->edge[l] * h->edge[l];
     const int S = splits_for((int)Ml, 4096);
-    CK(gemm(ch[l], h->Kp[l], (int)Ml, db, 1, ch[l], h->col[l], 1, h->Kp[l], h->scratch, S, h->s));
+    if (l > 1 && implicit_conv(h, l))
+      CK(gemm_conv_wgrad(ch[l], h->Kp[l], (int)Ml, db, conv_operand(h, l), h->scratch, S, h->s));
+    else
+      CK(gemm(ch[l], h->Kp[l], (int)Ml, db, 1, ch[l], h->col[l], 1, h->Kp[l], h->scratch, S, h->s));
     int Sused;
     {
       int chunk = ((int)Ml + S - 1) / S;

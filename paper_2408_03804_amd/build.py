@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfft_homog.so")
-SOURCES = ["kernels.hip", "kernels_chirp.hip", "fft_homog.hip", "cnn.hip", "launch_geometry.cpp", "noalloc_scratch.hip"]
+SOURCES = ["kernels.hip", "kernels_chirp.hip", "kernels_fixed.hip", "fft_homog.hip", "cnn.hip", "launch_geometry.cpp", "noalloc_scratch.hip"]
 HEADERS = ["common.h", "dual.h", "materials.h", "fft_lds.h", "kernels.h", "pass_kernels.h"]
 
 FLAGS = [
@@ -31,7 +31,8 @@ FLAGS = [
 # forward x pass's time.  They also let the compiler assume no NaN or Inf, so every domain and
 # breakdown test in those kernels is an integer test on the exponent bits (finite_bits).
 PER_FILE = {"kernels.hip": ["-ffinite-math-only", "-fno-signed-zeros"],
-            "kernels_chirp.hip": ["-ffinite-math-only", "-fno-signed-zeros"]}
+            "kernels_chirp.hip": ["-ffinite-math-only", "-fno-signed-zeros"],
+            "kernels_fixed.hip": ["-ffinite-math-only", "-fno-signed-zeros"]}
 
 
 def hipcc():

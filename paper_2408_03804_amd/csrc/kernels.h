@@ -153,6 +153,15 @@ hipError_t launch_xinv_chirp(int cons, const XInvArgs& a, dim3 grid, size_t sm, 
 hipError_t launch_mid_chirp(int dir, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s);
 hipError_t launch_outer_chirp(int mode, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s);
 hipError_t set_smem_limits_chirp(const Geom& g, int mat, size_t bytes);
+// the CG-loop pass kernels for single axis lengths with compiled schedules (kernels_fixed.hip):
+// lengths that have them; each launcher sets *done when it launched (else the caller launches the
+// generic kernel)
+bool fixed_len_kernels(int n);
+hipError_t launch_xfwd_fixed(int prod, int mat, const XFwdArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done);
+hipError_t launch_xinv_fixed(int cons, const XInvArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done);
+hipError_t launch_mid_fixed(int dir, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done);
+hipError_t launch_outer_fixed(int mode, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done);
+hipError_t set_smem_limits_fixed(const Geom& g, int mat, size_t bytes);
 
 // Scratch of the allocation-free projection: a file-scope device array of this many bytes per
 // device (noalloc_scratch.hip); its address on the current device.

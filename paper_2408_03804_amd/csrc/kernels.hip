@@ -404,6 +404,11 @@ hipError_t launch_xfwd(int prod, int mat, const XFwdArgs& a, int B, hipStream_t 
   dim3 grid(nblk_rows(a.g, a.R), B);
   const size_t sm = xfwd_smem(a.g, a.R, a.inplace);
   if (a.px.m > 0) return launch_xfwd_chirp(prod, mat, a, grid, sm, s);
+  if (a.inplace && a.g.ndim == 3 && fixed_len_kernels(a.px.n)) {
+    bool done = false;
+    const hipError_t e = launch_xfwd_fixed(prod, mat, a, grid, sm, s, &done);
+    if (done) return e;
+  }
   if (prod == PROD_CGOP && x_fixed128(a.g, a.px, a.R, a.inplace)) {
 #define FH_C(M, D) hipLaunchKernelGGL((k_xfwd<PROD_CGOP, M, D, (D == 3 ? 128 : 0)>), grid, dim3(kThreads), sm, s, a);
     FH_DISPATCH_MAT(mat, FH_C)
@@ -417,6 +422,11 @@ hipError_t launch_xinv(int cons, const XInvArgs& a, int B, hipStream_t s) {
   dim3 grid(nblk_rows(a.g, a.R), B);
   const size_t sm = xinv_smem(a.g, a.R, a.inplace);
   if (a.px.m > 0) return launch_xinv_chirp(cons, a, grid, sm, s);
+  if (a.inplace && a.g.ndim == 3 && fixed_len_kernels(a.px.n)) {
+    bool done = false;
+    const hipError_t e = launch_xinv_fixed(cons, a, grid, sm, s, &done);
+    if (done) return e;
+  }
   if (cons == CONS_CGUPD && x_fixed128(a.g, a.px, a.R, a.inplace) && (a.g.c == 9 || a.g.c == 6)) {
     if (a.g.c == 9) hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 9, 128>), grid, dim3(kThreads), sm, s, a);
     else hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 6, 128>), grid, dim3(kThreads), sm, s, a);
@@ -430,6 +440,11 @@ hipError_t launch_mid(int dir, const AxisArgs& a, int B, hipStream_t s) {
   dim3 grid(kx_tiles(a.g.nxh, a.TX), (a.g.nz + a.ZB - 1) / a.ZB, B * (rows ? 3 : a.g.c));
   const size_t sm = mid_smem(a.g, a.TX, a.inplace, a.ZB, a.proj);
   if (a.pl.m > 0) return launch_mid_chirp(dir, rows, a, grid, sm, s);
+  if (a.inplace && fixed_len_kernels(a.pl.n)) {
+    bool done = false;
+    const hipError_t e = launch_mid_fixed(dir, rows, a, grid, sm, s, &done);
+    if (done) return e;
+  }
   // the benchmark's axis length gets its own kernels when every stage keeps one butterfly per thread
   if (rows && a.inplace && a.pl.n == 128 && fixed_one_ok(128, mid_sequences(a.g, a.TX, a.ZB, a.proj))) {
     if (dir < 0) hipLaunchKernelGGL((k_mid_frow<-1, 128>), grid, dim3(kThreads), sm, s, a);
@@ -456,6 +471,11 @@ hipError_t launch_outer(int mode, const AxisArgs& a_in, int B, hipStream_t s) {
   const size_t sm = outer_smem(a.g, a.TX, a.inplace, mode);
   const bool rows = mode == OUTER_PROJECT && finite_rows(a.g);
   if (a.pl.m > 0) return launch_outer_chirp(mode, rows, a, grid, sm, s);
+  if (a.inplace && fixed_len_kernels(a.pl.n)) {
+    bool done = false;
+    const hipError_t e = launch_outer_fixed(mode, rows, a, grid, sm, s, &done);
+    if (done) return e;
+  }
   if (rows && a.inplace && a.pl.n == 128 && fixed_one_ok(128, G * kx_tile_max(a.g.nxh, a.TX))) {
     hipLaunchKernelGGL((k_outer_frow<128>), grid, dim3(kThreads), sm, s, a);
     return hipGetLastError();
@@ -639,6 +659,7 @@ hipError_t set_smem_limits(const Geom& g, int mat, size_t bytes) {
 #undef FH_SET
   if (e == hipSuccess && (g.lx != g.nx || g.lo != g.n_outer || (g.ndim == 3 && g.lm != g.ny)))
     e = set_smem_limits_chirp(g, mat, bytes);
+  if (e == hipSuccess) e = set_smem_limits_fixed(g, mat, bytes);
   return e;
 }
 

@@ -66,14 +66,21 @@ __device__ __forceinline__ void load_local(const MatParams& m, long long v, Loca
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // FFT variant of a pass kernel (template parameter NF):
-constexpr int kChirp = -1;  // chirp-z transform (plans with m > 0; kernels_chirp.hip)
-// NF > 0: a kernel specialised for axis length NF with one butterfly per thread per stage -- only
-// that length's code and a butterfly's registers (the launchers check fixed_one_ok); NF = 0: any
-// length with direct stages, with the register staging or the ping-pong buffer the host chose.
-// The buffers hold lds_len(pl) rows per sequence.
+//   0              any length with direct stages, with the register staging or the ping-pong
+//                  buffer the host chose;
+//   kChirp         the chirp-z transform (plans with m > 0; kernels_chirp.hip);
+//   L, 0 < L < kStaged   length L only, one butterfly per thread per stage (the launchers check
+//                  fixed_one_ok): only that length's code and a butterfly's registers;
+//   kStaged + L    length L only (a compiled schedule), register staging of up to kInplaceElems
+//                  elements per thread (the host chose in-place stages; kernels_fixed.hip).
+// The generic kernels hold every compiled schedule, and their registers follow the longest one;
+// the length-specific kernels hold one.  The buffers hold lds_len(pl) rows per sequence.
+constexpr int kChirp = -1;
+constexpr int kStaged = 1 << 12;
 template <int D, int NF>
 __device__ __forceinline__ void pass_fft(double2* A, double2* Bf, int nseq, const AxisPlan& pl, int inplace) {
-  if constexpr (NF > 0) fft_fixed_one<NF, D>(A, nseq, pl.tw);
+  if constexpr (NF > kStaged) fixed_stages<NF - kStaged, D, 0, 1>(A, nseq, make_fastdiv((unsigned)nseq), pl.tw);
+  else if constexpr (NF > 0) fft_fixed_one<NF, D>(A, nseq, pl.tw);
   else if constexpr (NF == kChirp) fft_chirp<D>(A, Bf, nseq, pl, inplace);
   else fft_lds_any<D>(A, Bf, nseq, pl, inplace);
 }

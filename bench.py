@@ -240,6 +240,54 @@ def bench_cells(args, name, cells, description):
     print(json.dumps(out), flush=True)
 
 
+def surrogate_flops_per_cell(n=32, channels=(1, 32, 64, 128, 256), hidden=256, n_feat=1, n_out=21):
+    """Multiply-add flops (2 per product) of one forward pass of one member: the conv blocks as the
+    GEMMs [outputs x 27 Ci] . [27 Ci x Co] and the two dense layers."""
+    f, e = 0, n
+    for l in range(1, 5):
+        e //= 2
+        f += 2 * e ** 3 * channels[l] * 27 * channels[l - 1]
+    return f + 2 * (channels[4] + n_feat) * hidden + 2 * hidden * n_out
+
+
+def cpu_surrogate_sample(sur, phase, tables, reject_frac, budget_s):
+    """The with-fallback job on the CPU oracle: both members' float64 forward passes (oracle/surrogate.py)
+    on the first cells until the budget, plus the oracle tangent of one cell times the rejected fraction
+    (the cells the indicator sends to the solver)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import newton_cg
+    from oracle import surrogate as OS
+    from paper_2408_03804_amd.surrogate import StiffnessSurrogate
+
+    kw = dict(channels=OS.CHANNELS, hidden=256, n_feat=1, n_out=21)
+    thetas = [net.get_params().cpu().numpy().astype(np.float64) for net in sur.nets]
+    done, t = 0, 0.0
+    while t < budget_s and done < phase.shape[0]:
+        ph = phase[done:done + 4].cpu().numpy()
+        ft = StiffnessSurrogate.features(tables[done:done + 4])
+        t0 = time.perf_counter()
+        for th in thetas:
+            OS.predict(th, ph, ft, **kw)
+        t += time.perf_counter() - t0
+        done += ph.shape[0]
+    t_sur = t / done
+    ph0 = phase[0].cpu().numpy()
+    tab = np.asarray(tables[0])
+    prob = newton_cg.Problem(ph0.shape, "linear_elastic", tab[ph0, 0], tab[ph0, 1])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        newton_cg.homogenized_tangent(prob, newton_cg.initial_state(prob), tol_cg=1e-10)
+        t_tan = time.perf_counter() - t0
+    per_cell = t_sur + reject_frac * t_tan
+    import torch
+    return {"value": 1.0 / per_cell, "unit": "tangents/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "float64 forward passes of the %d members on %d held-out cells (torch CPU, %d threads, "
+                      "%.1f s) plus %.3f x the oracle tangent of one cell (6 textbook CG solves, one thread, "
+                      "%.1f s) for the rejected fraction" % (len(thetas), done, torch.get_num_threads(), t,
+                                                             reject_frac, t_tan)}
+
+
 def bench_surrogate(args):
     """Stiffness surrogate against the solver on 32^3 cells: training data from the solver, training,
     held-out error, and tangents/s of both (surrogate with its indicator and solver fallback)."""
@@ -379,6 +427,17 @@ def bench_surrogate(args):
         "roofline": None,
         "cpu_baseline": None,
     }
+    # the surrogate's own kernels: bf16 MFMA work of both members' forward passes over the
+    # surrogate-only time (the indicator's work is negligible beside it)
+    fl = surrogate_flops_per_cell() * len(sur.nets) * nte / t_sur
+    out["roofline"] = {"bound": "mfma", "kernel": "surrogate inference: all layers of the %d members (effective)"
+                       % len(sur.nets), "achieved": round(fl / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                       "frac": round(fl / 2.5e15, 4), "traffic": None,
+                       "flops_per_cell_per_member": surrogate_flops_per_cell(),
+                       "note": "bf16 dense peak; the with-fallback value is dominated by the FP64 solver on the "
+                               "rejected cells (solver rooflines: the nh128 and tangents32 lines)"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_surrogate_sample(sur, tp, tt, float((~okh).mean()), args.cpu_seconds)
     sur.close()
     print(json.dumps(out), flush=True)
 

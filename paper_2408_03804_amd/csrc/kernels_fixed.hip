@@ -13,24 +13,23 @@ namespace {
 
 template <int L>
 hipError_t xfwd_len(int prod, int mat, const XFwdArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done) {
-  *done = true;
-  if (prod != PROD_CGOP) return (*done = false, hipSuccess);
+  *done = prod == PROD_CGOP && (mat == 1 || mat == 3 || mat == 5 || mat == 7);
+  if (!*done) return hipSuccess;
   switch (mat) {
     case 1: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, MAT_LE, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a); break;
     case 3: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, MAT_NH, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a); break;
     case 5: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, MAT_STVK, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a); break;
-    case 7: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, MAT_J2, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a); break;
-    default: *done = false; return hipSuccess;
+    default: hipLaunchKernelGGL((k_xfwd<PROD_CGOP, MAT_J2, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a); break;
   }
   return hipGetLastError();
 }
 
 template <int L>
 hipError_t xinv_len(int cons, const XInvArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done) {
-  *done = true;
-  if (cons == CONS_CGUPD && a.g.c == 6) hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 6, kStaged + L>), grid, dim3(kThreads), sm, s, a);
-  else if (cons == CONS_CGUPD && a.g.c == 9) hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 9, kStaged + L>), grid, dim3(kThreads), sm, s, a);
-  else return (*done = false, hipSuccess);
+  *done = cons == CONS_CGUPD && (a.g.c == 6 || a.g.c == 9);
+  if (!*done) return hipSuccess;
+  if (a.g.c == 6) hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 6, kStaged + L>), grid, dim3(kThreads), sm, s, a);
+  else hipLaunchKernelGGL((k_xinv<CONS_CGUPD, 9, kStaged + L>), grid, dim3(kThreads), sm, s, a);
   return hipGetLastError();
 }
 
@@ -41,11 +40,10 @@ hipError_t mid_len(int dir, bool rows, const AxisArgs& a, dim3 grid, size_t sm, 
 
 template <int L>
 hipError_t outer_len(int mode, bool rows, const AxisArgs& a, dim3 grid, size_t sm, hipStream_t s, bool* done) {
-  *done = true;
+  *done = rows || (mode == OUTER_PROJECT && a.g.small && a.g.ndim == 3);
+  if (!*done) return hipSuccess;
   if (rows) hipLaunchKernelGGL((k_outer_frow<kStaged + L>), grid, dim3(kThreads), sm, s, a);
-  else if (mode == OUTER_PROJECT && a.g.small && a.g.ndim == 3)
-    hipLaunchKernelGGL((k_outer<OUTER_PROJECT, 1, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a);
-  else return (*done = false, hipSuccess);
+  else hipLaunchKernelGGL((k_outer<OUTER_PROJECT, 1, 3, kStaged + L>), grid, dim3(kThreads), sm, s, a);
   return hipGetLastError();
 }
 

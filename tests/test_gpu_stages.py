@@ -23,7 +23,9 @@ FFT_SHAPES = [(7, 5), (31, 31), (8, 12), (1, 9), (6, 10, 12), (9, 16, 15), (5, 6
               (2, 3, 80), (80, 4), (3, 160, 2), (160, 2, 3), (2, 192, 3), (192, 5),
               # lengths with large prime factors on each axis: chirp-z transforms (199, 257 and, on the
               # outer axis, 97) and direct prime stages (299 = 13 * 23, and 97 on the x axis)
-              (199, 6), (3, 257), (4, 199, 5), (299, 4), (2, 3, 199), (3, 97), (97, 3), (2, 5, 97), (4, 3, 257)]
+              (199, 6), (3, 257), (4, 199, 5), (299, 4), (2, 3, 199), (3, 97), (97, 3), (2, 5, 97), (4, 3, 257),
+              # the longest axes (1024 points; 1021 is prime: a 2048-point chirp-z convolution)
+              (1021, 2), (2, 1021), (1024, 3)]
 
 
 def make(shape, kin, mat, nphase=2, **kw):

@@ -101,8 +101,12 @@ enum { FFT_HOMOG_FIELD_STRAIN = 0, FFT_HOMOG_FIELD_STRESS = 1, FFT_HOMOG_FIELD_E
 
 typedef struct fft_homog_desc {
   int ndim;          /* 2 or 3 */
-  int n[3];          /* grid points along x, y, z; each 1..1024 (prime factors above 16 use a direct
-                        DFT stage of that length: correct, but slower per point than radix stages) */
+  int n[3];          /* grid points along x, y, z; each 1..1024.  Factors 2, 3, 5 run radix stages;
+                        other prime factors run a direct DFT stage of that length, or, when those
+                        lengths add up to more than 70 (outer axis) or 150 (x and y axes), the axis
+                        runs the chirp-z (Bluestein) transform through cyclic convolutions of a
+                        length m >= 2n - 1 with factors 2, 3, 5 (more LDS per sequence; if its
+                        buffers do not fit, every axis keeps the direct stages) */
   double len[3];     /* cell edge lengths along x, y, z (> 0); wavevector xi = 2 pi k / len */
   int kinematics;    /* FFT_HOMOG_SMALL_STRAIN or FFT_HOMOG_FINITE_STRAIN */
   int material;      /* LINEAR_ELASTIC or J2_PLASTIC (small), NEO_HOOKEAN or STVK (finite); J2

@@ -1,6 +1,7 @@
 // Host-only exercise of the C ABI's host logic under AddressSanitizer and UndefinedBehaviorSanitizer:
-// descriptor validation and workspace layout over many grids, the CG chunk policy, status strings
-// and the argument checks that every entry point makes before it touches a device.  Built from
+// descriptor validation and workspace layout over many grids, the FFT plans (direct stages and the
+// chirp-z form) of every axis length, the CG chunk policy, status strings and the argument checks
+// that every entry point makes before it touches a device.  Built from
 // the library's own sources with host-only compilation (no device code, no GPU needed) by
 // tests/test_host_sanitized.py; exits non-zero if an expectation fails.
 #include <cmath>
@@ -10,6 +11,7 @@
 #include <initializer_list>
 
 #include "fft_homog.h"
+#include "kernels.h"
 
 static int failures = 0;
 #define EXPECT(cond)                                                        \
@@ -123,6 +125,57 @@ int main() {
               const int m = fft_homog_debug_cg_chunk(it, rr0, rr, tol, prev, prr);
               EXPECT(m >= 1 && m <= 16);
             }
+  // FFT plans of every axis length: the stages multiply out to the length they run on; a chirp-z
+  // plan has a convolution length m >= 2n - 1 with factors 2, 3, 5 only and register-stageable
+  // radices, and is chosen only when the direct prime stages add up to more than the threshold
+  for (int lim : {0, 70, 150}) {
+    for (int n = 1; n <= 1024; ++n) {
+      fh::AxisPlan pl;
+      EXPECT(fh::make_plan(n, &pl, lim));
+      const int L = fh::lds_len(pl);
+      long long prod = 1;
+      int primes = 0;
+      EXPECT(pl.nstages >= 0 && pl.nstages <= fh::kMaxStages);
+      for (int st = 0; st < pl.nstages; ++st) prod *= pl.radix[st];
+      EXPECT(prod == L || (n == 1 && L == 1));
+      int q = n;
+      for (int p = 2; q > 1; ++p)
+        while (q % p == 0) {
+          if (p > 5) primes += p;
+          q /= p;
+        }
+      if (pl.m > 0) {
+        EXPECT(lim > 0 && primes > lim);
+        EXPECT(pl.m >= 2 * n - 1 && pl.m <= 2048);
+        int r = pl.m;
+        for (int p : {2, 3, 5})
+          while (r % p == 0) r /= p;
+        EXPECT(r == 1);
+        for (int st = 0; st < pl.nstages; ++st) EXPECT(pl.radix[st] <= 16 && pl.radix[st] != 7);
+        EXPECT(fh::plan_table_elems(pl) == (size_t)(pl.m + n + pl.m));
+      } else {
+        EXPECT(lim == 0 || primes <= lim || 2 * n - 1 > 2048);
+        EXPECT(fh::plan_table_elems(pl) == (size_t)n);
+      }
+    }
+  }
+  {
+    fh::AxisPlan pl;
+    fh::make_plan(199, &pl, 150);
+    EXPECT(pl.m == 400);
+    fh::make_plan(97, &pl, 70);
+    EXPECT(pl.m == 200);
+    fh::make_plan(97, &pl, 150);
+    EXPECT(pl.m == 0 && pl.nstages == 1 && pl.radix[0] == 97);
+    fh::make_plan(299, &pl, 70);
+    EXPECT(pl.m == 0);  // 13 + 23 = 36
+    fh::make_plan(511, &pl, 70);
+    EXPECT(pl.m == 1024);  // 7 + 73 = 80
+    fh::make_plan(1021, &pl, 150);
+    EXPECT(pl.m == 2048);
+    fh::make_plan(128, &pl, 70);
+    EXPECT(pl.m == 0 && pl.nstages == 2 && pl.radix[0] == 16 && pl.radix[1] == 8);
+  }
   std::printf("host checks: %lld descriptors, %d failures\n", checked, failures);
   return failures == 0 ? 0 : 1;
 }

@@ -246,8 +246,8 @@ __device__ double2* fft_lds(double2* a, double2* b, int nseq, const AxisPlan& pl
 }
 
 // ---- in-place variant: register-staged stages, one LDS buffer ---------------
-// Every stage first loads all butterfly inputs of the thread into registers,
-// synchronises, then writes the outputs to their Stockham positions in the same
+// Every stage first loads all butterfly inputs of the thread into registers and computes its
+// butterflies, synchronises, then writes the outputs to their Stockham positions in the same
 // buffer.  Usable when all radices are 2/3/4/5/8 and no thread owns more than
 // kInplaceElems elements in a stage (checked by the host: inplace_ok()).
 
@@ -261,14 +261,26 @@ __device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nse
   const int total = nb * nseq;
   const FastDiv fdn = make_fastdiv((unsigned)Ns);
   double2 v[MB][R];
+  int ov[MB], sv[MB];
+  // butterflies in registers before the barrier, which only guards the in-place write
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
+    ov[i] = 0;
+    sv[i] = 0;
     if (w < total) {
       const int j = (int)fdiv((unsigned)w, fdq);
       const int s = w - j * nseq;
+      const int k = j - (int)fdiv((unsigned)j, fdn) * Ns;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = buf[(j + t * nb) * nseq + s];
+      if (Ns > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * stride));
+      }
+      dft_small<R, DIR>(v[i]);
+      ov[i] = (j - k) * R + k;
+      sv[i] = s;
     }
   }
   __syncthreads();
@@ -276,17 +288,8 @@ __device__ __forceinline__ void stage_inplace(double2* __restrict__ buf, int nse
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
     if (w < total) {
-      const int j = (int)fdiv((unsigned)w, fdq);
-      const int s = w - j * nseq;
-      const int k = j - (int)fdiv((unsigned)j, fdn) * Ns;
-      if (Ns > 1) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * stride));
-      }
-      dft_small<R, DIR>(v[i]);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[(base + t * Ns) * nseq + s] = v[i][t];
+      for (int t = 0; t < R; ++t) buf[(ov[i] + t * Ns) * nseq + sv[i]] = v[i][t];
     }
   }
   __syncthreads();
@@ -303,19 +306,27 @@ __device__ __forceinline__ void stage_fixed(double2* __restrict__ buf, int nseq,
   constexpr int STRIDE = N / (NS * R);
   const int total = NB * nseq;
   double2 v[MB][R];
-  int jv[MB], sv[MB];
+  int ov[MB], sv[MB];
+  // each thread's butterflies are computed in registers before the barrier (their twiddle loads
+  // and arithmetic overlap the other waves' LDS reads); the barrier only guards the in-place write
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
-    jv[i] = 0;
+    ov[i] = 0;
     sv[i] = 0;
     if (w < total) {
       const int j = (int)fdiv((unsigned)w, fd);
       const int s = w - j * nseq;
-      jv[i] = j;
-      sv[i] = s;
+      const int k = j % NS;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = buf[(j + t * NB) * nseq + s];
+      if (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * STRIDE));
+      }
+      dft_small<R, DIR>(v[i]);
+      ov[i] = (j - k) * R + k;
+      sv[i] = s;
     }
   }
   __syncthreads();
@@ -323,17 +334,8 @@ __device__ __forceinline__ void stage_fixed(double2* __restrict__ buf, int nseq,
   for (int i = 0; i < MB; ++i) {
     const int w = threadIdx.x + i * blockDim.x;
     if (w < total) {
-      const int j = jv[i];
-      const int s = sv[i];
-      const int k = j % NS;
-      if (NS > 1) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], twiddle<DIR>(tw, t * k * STRIDE));
-      }
-      dft_small<R, DIR>(v[i]);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[(base + t * NS) * nseq + s] = v[i][t];
+      for (int t = 0; t < R; ++t) buf[(ov[i] + t * NS) * nseq + sv[i]] = v[i][t];
     }
   }
   __syncthreads();

@@ -1,6 +1,7 @@
 // The pass kernels of the Fourier-Galerkin Newton-CG solve for gfx950 (FP64), as templates:
 // kernels.hip instantiates them with the direct FFT stages (and the kernels specialised for
-// 128-point axes), kernels_chirp.hip with the chirp-z transform.
+// 128-point axes), kernels_fixed.hip for 96-, 64-, 48- and 32-point axes, kernels_chirp.hip with
+// the chirp-z transform.
 //
 // One CG iteration (section 3 equilibrium operator, section 3.2 incremental
 // stress, Appendix A linear solve) is five passes over the data:

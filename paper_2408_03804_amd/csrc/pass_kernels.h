@@ -92,6 +92,28 @@ __device__ __forceinline__ void pass_fft(double2* A, double2* Bf, int nseq, cons
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
+// Gather n complex entries into LDS: dst[i] = v for (v, i) = src(t), t < n.  Each thread issues up
+// to S global loads before its first LDS write, so that S of its loads are in flight together (in
+// a plain load-then-write loop each load waits for the previous one).  Used where it measured
+// faster: the inverse x pass and the plain y pass; the row-wise y and outer passes, which run at
+// their register caps, were slower with it.
+template <int S, typename Src>
+__device__ __forceinline__ void gather_staged(double2* dst, int n, Src src) {
+  for (int base = 0; base < n; base += S * kThreads) {
+    double2 v[S];
+    int di[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const int t = base + (int)threadIdx.x + e * kThreads;
+      di[e] = -1;
+      if (t < n) v[e] = src(t, &di[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < S; ++e)
+      if (di[e] >= 0) dst[di[e]] = v[e];
+  }
+}
+
 // ============================================================================
 // CG scalar bookkeeping from a reduced sum (fixed-order two-stage sums)
 // ============================================================================
@@ -200,19 +222,30 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         load_local<MAT, NDIM>(mat, vox, L);  // brings the phase id and table line into cache
         (void)L;
       }
+      // r, p and x are distinct buffers: every load is issued before the first store (without the
+      // restrict qualifiers the compiler must order each component's loads after the previous
+      // component's stores, one memory round trip per component)
+      const double* __restrict__ rin = a.in + (long long)b * C * N + vox;
+      double* __restrict__ pio = a.p + (long long)b * C * N + vox;
+      double* __restrict__ xio = a.x + (long long)b * C * N + vox;
+      double rv[C], pv[C], xv[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) rv[j] = ld_stream(rin + j * N);
+      if (!first) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          pv[j] = ld_stream(pio + j * N);
+          xv[j] = ld_stream(xio + j * N);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const long long idx = ((long long)b * C + j) * N + vox;
-        const double rj = ld_stream(a.in + idx);
-        double pj;
-        if (first) {
-          pj = rj;
-        } else {
-          const double po = ld_stream(a.p + idx);
-          st_stream(a.x + idx, ld_stream(a.x + idx) + alpha_prev * po);
-          pj = rj + beta * po;
+        double pj = rv[j];
+        if (!first) {
+          st_stream(xio + j * N, xv[j] + alpha_prev * pv[j]);
+          pj = rv[j] + beta * pv[j];
         }
-        st_stream(a.p + idx, pj);
+        st_stream(pio + j * N, pj);
         *slot(j, r, x) = pj;
       }
     }
@@ -376,13 +409,14 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
 
   const FastDiv fdh = make_fastdiv((unsigned)nxh);
   const FastDiv fdp = make_fastdiv((unsigned)P);
-  for (int t = threadIdx.x; t < nseq * nxh; t += blockDim.x) {
+  gather_staged<8>(H, nseq * nxh, [&](int t, int* di) {
     const int qr = (int)fdiv((unsigned)t, fdh);
     const int k = t - qr * nxh;
     const int j = qr / nr;
     const int r = qr - j * nr;
-    H[k * nseq + qr] = a.spec[((long long)b * C + j) * g.Nh + (long long)(row0 + r) * g.nxp + k];
-  }
+    *di = k * nseq + qr;
+    return a.spec[((long long)b * C + j) * g.Nh + (long long)(row0 + r) * g.nxp + k];
+  });
   __syncthreads();
   for (int t = threadIdx.x; t < P * nx; t += blockDim.x) {
     const int k = (int)fdiv((unsigned)t, fdp);
@@ -418,6 +452,14 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     const int r = t / nx;
     const int x = t - r * nx;
     const long long vox = (long long)(row0 + r) * nx + x;
+    // the residual's components are all loaded before the first store (restrict: no component's
+    // store has to wait for the next one's load)
+    double* __restrict__ rio = a.r + (long long)b * C * N + vox;
+    double rv[C];
+    if (CONS == CONS_CGUPD) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) rv[j] = pre ? rpre[j] : ld_stream(rio + j * N);
+    }
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const int qr = j * nr + r;
@@ -431,8 +473,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
         a.x[idx] = 0.0;
         acc += u * u;
       } else {
-        const double rn = (pre ? rpre[j] : ld_stream(a.r + idx)) - alpha * u;
-        st_stream(a.r + idx, rn);
+        const double rn = rv[j] - alpha * u;
+        st_stream(rio + j * N, rn);
         acc += rn * rn;
       }
     }
@@ -466,13 +508,14 @@ __global__ void __launch_bounds__(kThreads) k_mid(AxisArgs a) {
   const long long base = ((long long)b * g.c + comp) * g.Nh + (long long)z0 * ny * g.nxp + kx0;
   const FastDiv fdq = make_fastdiv((unsigned)nseq);
   const FastDiv fdt = make_fastdiv((unsigned)tw);
-  for (int t = threadIdx.x; t < ny * nseq; t += blockDim.x) {
+  gather_staged<8>(A, ny * nseq, [&](int t, int* di) {
     const int y = (int)fdiv((unsigned)t, fdq);
     const int q = t - y * nseq;
     const int zz = (int)fdiv((unsigned)q, fdt);
     const int s = q - zz * tw;
-    A[t] = a.spec[base + (long long)(zz * ny + y) * g.nxp + s];
-  }
+    *di = t;
+    return a.spec[base + (long long)(zz * ny + y) * g.nxp + s];
+  });
   __syncthreads();
   pass_fft<DIR, NF>(A, Bf, nseq, a.pl, a.inplace);
   for (int t = threadIdx.x; t < ny * nseq; t += blockDim.x) {

@@ -51,6 +51,10 @@ def test_2d_and_request_beyond_the_scratch():
     shape = (31, 31)
     x = torch.as_tensor(np.random.default_rng(3).standard_normal((1, 3) + shape)).cuda()
     assert field_err(noalloc(shape, "small", "linear_elastic", x), reference(shape, "small", "linear_elastic", x)) < 1e-13
+    # axes that take the chirp-z transform (its tables live in the scratch too): x in 2D, outer in 3D
+    for shp, kin, mat, c in (((199, 8), "small", "linear_elastic", 3), ((4, 5, 97), "finite", "neo_hookean", 9)):
+        xc = torch.as_tensor(np.random.default_rng(5).standard_normal((1, c) + shp)).cuda()
+        assert field_err(noalloc(shp, kin, mat, xc), reference(shp, kin, mat, xc)) < 1e-13, shp
     # 128^3 finite strain: a 170 MB half spectrum does not fit the 64 MiB scratch
     big = (128, 128, 128)
     d = binding.make_desc(big, "finite", "neo_hookean", 2)

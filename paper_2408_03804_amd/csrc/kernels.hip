@@ -31,9 +31,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_cg_reduce(CgState* st, const
   const int b = active ? active[blockIdx.x] : (int)blockIdx.x;
   CgState& S = st[b];
   if (WHAT == RED_RR && S.status != CG_RUNNING) return;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partials[(long long)b * nblocks + i];
-  const double s = block_sum(acc, red);
+  const double s = block_sum(strided_sum<8, kReduceThreads>(partials + (long long)b * nblocks, nblocks), red);
   if (threadIdx.x == 0) cg_finalize<WHAT>(S, s);
 }
 

@@ -92,6 +92,24 @@ __device__ __forceinline__ void pass_fft(double2* A, double2* Bf, int nseq, cons
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
+// Sum of x[tid], x[tid + kThreads], x[tid + 2 kThreads], ... (i < n) in that order, with up to S of
+// the thread's loads in flight together; bitwise the strided loop's sum.
+template <int S, int BD>
+__device__ __forceinline__ double strided_sum(const double* __restrict__ x, int n) {
+  double acc = 0.0;
+  for (int base = 0; base < n; base += S * BD) {
+    double v[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const int i = base + (int)threadIdx.x + e * BD;
+      v[e] = i < n ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < S; ++e) acc += v[e];
+  }
+  return acc;
+}
+
 // Gather n complex entries into LDS: dst[i] = v for (v, i) = src(t), t < n.  Each thread issues up
 // to S global loads before its first LDS write, so that S of its loads are in flight together (in
 // a plain load-then-write loop each load waits for the previous one).  Used where it measured
@@ -642,10 +660,7 @@ __global__ void __launch_bounds__(kThreads) k_outer(AxisArgs a) {
     // <p, K:p> and alpha of right-hand side b, summed in a fixed order; nothing in this
     // pass reads them (the inverse x pass does)
     __shared__ double red[kThreads / 64];
-    const double* pp = a.pq_partials + (long long)b * a.pq_nblocks;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < a.pq_nblocks; i += blockDim.x) acc += pp[i];
-    const double s = block_sum(acc, red);
+    const double s = block_sum(strided_sum<8, kThreads>(a.pq_partials + (long long)b * a.pq_nblocks, a.pq_nblocks), red);
     if (threadIdx.x == 0) cg_finalize<RED_PQ>(a.pq_st[b], s);
   }
   const int kx0 = bx * a.TX;
@@ -889,10 +904,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
   if (a.pq_st != nullptr && bx == 0 && by == 0 && row == 0) {
     // <p, K:p> and alpha of right-hand side b, summed in a fixed order (read by the inverse x pass)
     __shared__ double red[kThreads / 64];
-    const double* pp = a.pq_partials + (long long)b * a.pq_nblocks;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < a.pq_nblocks; i += blockDim.x) acc += pp[i];
-    const double sum = block_sum(acc, red);
+    const double sum = block_sum(strided_sum<8, kThreads>(a.pq_partials + (long long)b * a.pq_nblocks, a.pq_nblocks), red);
     if (threadIdx.x == 0) cg_finalize<RED_PQ>(a.pq_st[b], sum);
   }
   const int kx0 = bx * a.TX;

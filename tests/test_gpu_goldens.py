@@ -51,7 +51,7 @@ def test_spheres_64_tangent_matches_oracle():
         assert abs(a - b) <= 1, (st["cg"], g["cg_per_load"])
 
 
-@pytest.mark.parametrize("n", [64])
+@pytest.mark.parametrize("n", [64, 128])  # 128: the benchmark workload itself (9.2 h of oracle time)
 def test_neohookean_grf_matches_oracle(n):
     g = load("nh3d_grf_%d" % n)
     smp = np.load(os.path.join(GOLDEN, "nh3d_grf_%d_samples.npz" % n))
@@ -67,11 +67,17 @@ def test_neohookean_grf_matches_oracle(n):
     Sref = np.asarray(g["macro_stress"])
     assert np.abs(S - Sref).max() < TOL_HOMOG * np.abs(Sref).max()
     assert abs(psi - g["energy"]) < TOL_HOMOG * abs(g["energy"])
-    # iteration counts (the AD-vs-analytic identity: equal to within one at threshold crossings)
+    # iteration counts (the AD-vs-analytic identity: equal up to threshold crossings).  The GPU takes
+    # <p, q> as <p, K:p> (equal in exact arithmetic, not in rounding); at 128^3 the last CG solve of
+    # an increment, whose right-hand side is a converged Newton residual, crosses 1e-12 where that
+    # rounding difference has moved one solve by two iterations (39 of 40 solves identical, totals
+    # 4609 vs 4607)
+    it_tol = 1 if n <= 64 else 2
     assert abs(st["newton"] - g["newton"]) <= 1
     if st["newton"] == g["newton"]:
         for a, b in zip(st["cg"], g["cg"]):
-            assert abs(a - b) <= 1, (st["cg"], g["cg"])
+            assert abs(a - b) <= it_tol, (st["cg"], g["cg"])
+        assert abs(st["cg_total"] - g["cg_total"]) <= max(2, 1e-3 * g["cg_total"])
     # the converged field at the seeded voxels, as fluctuations about the macro load
     F = h.get_field(0).cpu().numpy().reshape(9, -1)[:, smp["index"]].T
     Fbar = w["macro"].reshape(1, 9)

@@ -613,8 +613,9 @@ def main():
     h.set_material(w["phase"], w["table"])
     shape_info = h.launch_shape()
     if args.autotune:
-        # launch-shape tuning is set-up work, outside the timed region (at 128^3 it finds
-        # nothing better than the default shape, which the committed profile covers)
+        # launch-shape tuning is set-up work, outside the timed region (at 128^3 its gain is
+        # within the spread between GPUs; the default shape is the one the parity test and
+        # the committed profile cover)
         shape_info = h.autotune(reps=10)
         log("launch shape: %s" % shape_info)
     ident = torch.zeros((9,) + shape, dtype=torch.float64, device="cuda:0")

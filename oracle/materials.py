@@ -18,6 +18,9 @@ Readings of the paper used here:
   strain E = (F^T F - I)/2, psi = lam/2 tr(E)^2 + mu E:E.
 * compressible Neo-Hookean (not written out in the paper):
   psi = mu/2 (I1 - 3) - mu ln J + lam/2 (ln J)^2, I1 = tr(F^T F).
+* plane stress (named with the 2D examples of section 4.4, not written out):
+  the 3D law with the out-of-plane entry chosen so that the out-of-plane
+  normal stress vanishes at each point, for every law here.
 """
 
 import numpy as np
@@ -207,11 +210,122 @@ class StVenantKirchhoff:
         return out
 
 
+# ----------------------------------------------------------------------------
+# finite strain under plane stress
+# ----------------------------------------------------------------------------
+# A 2D deformation gradient F2 is completed to F = [[F2, 0], [0, F33]]; the out-of-plane stretch F33
+# takes the value at which the 3D law's P33 vanishes.  For an isotropic law the out-of-plane shear
+# stresses vanish with the shear entries of F.  Stress and energy are those of the 3D law at that F
+# (the in-plane block of P).  The tangent is the 3D tangent condensed on dF33, the textbook static
+# condensation:  K_ps : dF2 = K_ab:dF - K_ab33 (K_33:dF) / K_3333.
+
+
+def _embed(F, F33):
+    out = np.zeros(F.shape[:-2] + (3, 3), dtype=np.result_type(F, F33))
+    out[..., :2, :2] = F
+    out[..., 2, 2] = F33
+    return out
+
+
+def _condensed_apply(K3, dF):
+    dF3 = _embed(dF, np.zeros(dF.shape[:-2]))
+    q = np.einsum("...ijkl,...kl->...ij", K3, dF3)
+    dF33 = -q[..., 2, 2] / K3[..., 2, 2, 2, 2]
+    return q[..., :2, :2] + K3[..., :2, :2, 2, 2] * dF33[..., None, None]
+
+
+class NeoHookeanPlaneStress:
+    """Neo-Hookean under plane stress.  With J = det(F2) F33, P33 F33 = mu F33^2 + lam ln J - mu is
+    increasing in F33 > 0 for lam >= 0, mu > 0 and runs from -inf to +inf, so its root is found by
+    bisection on a bracket grown from 1."""
+
+    kinematics = "finite"
+
+    @staticmethod
+    def stretch(F, lam, mu):
+        J2 = np.linalg.det(F)
+        lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), J2.shape)
+        mu = np.broadcast_to(np.asarray(mu, dtype=np.float64), J2.shape)
+
+        def h(s):
+            return mu * s * s + lam * np.log(J2 * s) - mu
+
+        lo = np.ones(J2.shape)
+        hi = np.ones(J2.shape)
+        for _ in range(2000):
+            m = h(lo) > 0
+            if not m.any():
+                break
+            lo = np.where(m, 0.5 * lo, lo)
+        for _ in range(2000):
+            m = h(hi) < 0
+            if not m.any():
+                break
+            hi = np.where(m, 2.0 * hi, hi)
+        for _ in range(4000):
+            mid = 0.5 * (lo + hi)
+            done = (mid <= lo) | (mid >= hi)
+            if done.all():
+                break
+            up = h(mid) > 0
+            hi = np.where(up & ~done, mid, hi)
+            lo = np.where(~up & ~done, mid, lo)
+        return 0.5 * (lo + hi)
+
+    @staticmethod
+    def full(F, lam, mu):
+        return _embed(F, NeoHookeanPlaneStress.stretch(F, lam, mu))
+
+    @staticmethod
+    def stress(F, lam, mu):
+        return NeoHookean.stress(NeoHookeanPlaneStress.full(F, lam, mu), lam, mu)[..., :2, :2]
+
+    @staticmethod
+    def psi(F, lam, mu):
+        return NeoHookean.psi(NeoHookeanPlaneStress.full(F, lam, mu), lam, mu)
+
+    @staticmethod
+    def tangent_apply(F, dF, lam, mu):
+        K3 = NeoHookean.tangent_tensor(NeoHookeanPlaneStress.full(F, lam, mu), lam, mu)
+        return _condensed_apply(K3, dF)
+
+
+class StVenantKirchhoffPlaneStress:
+    """St. Venant-Kirchhoff under plane stress.  P33 = F33 S33 and S33 = lam (E11 + E22) +
+    (lam + 2 mu) E33, so P33 = 0 fixes E33 = -lam (E11 + E22) / (lam + 2 mu) and
+    F33 = sqrt(1 + 2 E33)."""
+
+    kinematics = "finite"
+
+    @staticmethod
+    def full(F, lam, mu):
+        lam = np.asarray(lam, dtype=np.float64)
+        mu = np.asarray(mu, dtype=np.float64)
+        E = StVenantKirchhoff._green(F)
+        E33 = -lam * (E[..., 0, 0] + E[..., 1, 1]) / (lam + 2.0 * mu)
+        return _embed(F, np.sqrt(1.0 + 2.0 * E33))
+
+    @staticmethod
+    def stress(F, lam, mu):
+        return StVenantKirchhoff.stress(StVenantKirchhoffPlaneStress.full(F, lam, mu), lam, mu)[..., :2, :2]
+
+    @staticmethod
+    def psi(F, lam, mu):
+        return StVenantKirchhoff.psi(StVenantKirchhoffPlaneStress.full(F, lam, mu), lam, mu)
+
+    @staticmethod
+    def tangent_apply(F, dF, lam, mu):
+        K3 = StVenantKirchhoff.tangent_tensor(StVenantKirchhoffPlaneStress.full(F, lam, mu), lam, mu)
+        return _condensed_apply(K3, dF)
+
+
 MATERIALS = {
     "linear_elastic": LinearElastic,
     "linear_elastic_plane_stress": LinearElasticPlaneStress,
     "neo_hookean": NeoHookean,
     "stvk": StVenantKirchhoff,
+    "neo_hookean_plane_stress": NeoHookeanPlaneStress,
+    "stvk_plane_stress": StVenantKirchhoffPlaneStress,
 }
 
 

@@ -529,3 +529,83 @@ def test_plane_stress_is_the_3d_law_with_zero_out_of_plane_stress():
     one = np.zeros((1, 2, 2))
     one[0, 0, 0] = 1.0
     assert PS.stress(one, 1.0, 1.0)[0, 0, 0] < materials.LinearElastic.stress(one, 1.0, 1.0)[0, 0, 0]
+
+
+def _plane_stress_points(seed, n=12):
+    rng = np.random.default_rng(seed)
+    F = np.eye(2) + 0.25 * rng.standard_normal((n, 2, 2))
+    F = F[np.linalg.det(F) > 0.2]
+    lam, mu = rng.uniform(0.0, 4.0, len(F)), rng.uniform(0.3, 2.0, len(F))
+    dF = rng.standard_normal(F.shape)
+    dG = rng.standard_normal(F.shape)
+    return F, dF, dG, lam, mu
+
+
+@pytest.mark.parametrize("name,law", [("neo_hookean_plane_stress", materials.NeoHookean),
+                                      ("stvk_plane_stress", materials.StVenantKirchhoff)])
+def test_finite_plane_stress_is_the_3d_law_with_zero_out_of_plane_stress(name, law):
+    """Pins the finite-strain plane-stress oracle: the 3D law's P has no out-of-plane entries at the
+    completed F (P33 = 0 by the choice of F33, the shear entries by isotropy); the stress is the
+    energy's derivative (central differences of psi); the condensed tangent is the stress's
+    derivative and has the major symmetry; at small strain the law is the linear plane-stress one."""
+    mat = materials.MATERIALS[name]
+    F, dF, dG, lam, mu = _plane_stress_points(41, 24)
+    F3 = mat.full(F, lam, mu)
+    ok = np.isfinite(F3).all(axis=(-2, -1))  # St. Venant-Kirchhoff: a real F33 needs 1 + 2 E33 > 0
+    assert ok.sum() >= 12
+    F, dF, dG, lam, mu, F3 = F[ok], dF[ok], dG[ok], lam[ok], mu[ok], F3[ok]
+    P3 = law.stress(F3, lam, mu)
+    scale = np.abs(P3).max()
+    off = P3.copy()
+    off[..., :2, :2] = 0.0
+    assert np.abs(off).max() < 1e-13 * scale
+    P = mat.stress(F, lam, mu)
+    h = 1e-5
+    dpsi = (mat.psi(F + h * dF, lam, mu) - mat.psi(F - h * dF, lam, mu)) / (2 * h)
+    assert np.abs(dpsi - np.einsum("...ij,...ij->...", P, dF)).max() < 1e-8 * scale
+    KdF = mat.tangent_apply(F, dF, lam, mu)
+    fd = (mat.stress(F + h * dF, lam, mu) - mat.stress(F - h * dF, lam, mu)) / (2 * h)
+    assert np.abs(KdF - fd).max() < 1e-8 * np.abs(KdF).max()
+    KdG = mat.tangent_apply(F, dG, lam, mu)
+    a = np.einsum("...ij,...ij->...", dG, KdF)
+    b = np.einsum("...ij,...ij->...", dF, KdG)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    # linearisation about F = I: sigma = P at first order, the linear plane-stress law
+    t = 1e-7
+    H = 0.5 * (dF + np.swapaxes(dF, -1, -2))
+    lin = materials.LinearElasticPlaneStress.stress(H, lam, mu)
+    Pt = mat.stress(np.eye(2) + t * H, lam, mu) / t
+    assert np.abs(Pt - lin).max() < 1e-5 * np.abs(lin).max()
+
+
+def test_neo_hookean_plane_stress_stretch_is_the_root_brentq_finds():
+    """The out-of-plane stretch of the Neo-Hookean plane-stress oracle (bisection) against SciPy's
+    Brent root finder on mu s^2 + lam ln(J2 s) - mu = 0, point by point, over a wide range of J2."""
+    from scipy.optimize import brentq
+    rng = np.random.default_rng(42)
+    F = np.eye(2) * rng.uniform(0.3, 2.5, (40, 1, 1)) + 0.2 * rng.standard_normal((40, 2, 2))
+    F = F[np.linalg.det(F) > 0.05]
+    lam, mu = rng.uniform(0.0, 20.0, len(F)), rng.uniform(0.1, 3.0, len(F))
+    s = materials.NeoHookeanPlaneStress.stretch(F, lam, mu)
+    J2 = np.linalg.det(F)
+    for k in range(len(F)):
+        f = lambda x: mu[k] * x * x + lam[k] * np.log(J2[k] * x) - mu[k]  # noqa: E731
+        ref = brentq(f, 1e-8, 1e8, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+        assert abs(s[k] - ref) < 1e-14 * ref, (k, s[k], ref)
+    # equibiaxial stretch of an incompressible-like law shortens the thickness; lam = 0 keeps it
+    assert materials.NeoHookeanPlaneStress.stretch(1.2 * np.eye(2)[None], np.array([5.0]), np.array([1.0]))[0] < 1.0
+    assert materials.NeoHookeanPlaneStress.stretch(1.2 * np.eye(2)[None], np.array([0.0]), np.array([1.0]))[0] == 1.0
+
+
+def test_stvk_plane_stress_is_2d_stvk_with_reduced_lame_parameter():
+    """St. Venant-Kirchhoff's energy is quadratic in E, so eliminating E33 by S33 = 0 leaves the 2D law
+    with lam* = 2 lam mu / (lam + 2 mu), as in linear elasticity."""
+    F, dF, _, lam, mu = _plane_stress_points(43)
+    PS = materials.StVenantKirchhoffPlaneStress
+    law = materials.StVenantKirchhoff
+    ls = 2 * lam * mu / (lam + 2 * mu)
+    scale = np.abs(PS.stress(F, lam, mu)).max()
+    assert np.abs(PS.stress(F, lam, mu) - law.stress(F, ls, mu)).max() < 1e-13 * scale
+    assert np.abs(PS.psi(F, lam, mu) - law.psi(F, ls, mu)).max() < 1e-13 * np.abs(PS.psi(F, lam, mu)).max()
+    K = PS.tangent_apply(F, dF, lam, mu)
+    assert np.abs(K - law.tangent_apply(F, dF, ls, mu)).max() < 1e-12 * np.abs(K).max()

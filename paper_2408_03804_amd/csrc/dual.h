@@ -151,6 +151,17 @@ __host__ __device__ inline Dual<T, K> dsqrt(const Dual<T, K>& a) {
   return r;
 }
 
+__host__ __device__ inline double dexp(double a) { return exp(a); }
+
+template <class T, int K>
+__host__ __device__ inline Dual<T, K> dexp(const Dual<T, K>& a) {
+  Dual<T, K> r;
+  r.v = dexp(a.v);
+#pragma unroll
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * r.v;
+  return r;
+}
+
 __host__ __device__ inline double dlog(double a) { return log(a); }
 
 template <class T, int K>

@@ -87,6 +87,14 @@ bool make_geom(const fft_homog_desc* d, Geom* g) {
   return true;
 }
 
+// kernel material code: 2 * material + (ndim - 2); Neo-Hookean under plane stress has a law of its
+// own (8), linear elasticity and St. Venant-Kirchhoff under plane stress are their 2D laws with a
+// reduced first Lame parameter (set_material converts the table)
+static int material_code(const fft_homog_desc* d) {
+  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && d->material == FFT_HOMOG_NEO_HOOKEAN) return 8;
+  return 2 * d->material + (d->ndim - 2);
+}
+
 int validate_desc(const fft_homog_desc* d) {
   if (!d) return FFT_HOMOG_EINVAL;
   if (d->ndim != 2 && d->ndim != 3) return FFT_HOMOG_EINVAL;
@@ -111,7 +119,7 @@ int validate_desc(const fft_homog_desc* d) {
   if (d->batch < 0) return FFT_HOMOG_EINVAL;
   if (d->flags & ~(FFT_HOMOG_FLAG_TANGENT | FFT_HOMOG_FLAG_DENSITY | FFT_HOMOG_FLAG_GRAPH | FFT_HOMOG_FLAG_PLANE_STRESS))
     return FFT_HOMOG_EINVAL;
-  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && (d->ndim != 2 || d->material != FFT_HOMOG_LINEAR_ELASTIC))
+  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && (d->ndim != 2 || d->material == FFT_HOMOG_J2_PLASTIC))
     return FFT_HOMOG_EINVAL;
   if (d->batch > 1) {
     // a multi-cell handle runs the tangent solves of every cell at the reference state
@@ -774,7 +782,7 @@ int fft_homog_create(const fft_homog_desc* d, void* dev_workspace, size_t bytes,
   make_geom(d, &h->g);
   make_plans(d, L.chirp, h->plan, &h->g);
   h->L = L;
-  h->matcode = 2 * d->material + (d->ndim - 2);
+  h->matcode = material_code(d);
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char*)dev_workspace;
   h->F = (double*)(h->ws + L.F);
@@ -897,10 +905,17 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
     for (int ph = 0; ph < h->desc.nphase; ++ph)
       if (!(lm[4 * ph + 2] >= 0.0) || !(lm[4 * ph + 3] >= 0.0) || !(3.0 * lm[4 * ph + 1] + lm[4 * ph + 3] > 0.0))
         return fail(h, FFT_HOMOG_EINVAL, "J2 phase needs sig_y >= 0, H >= 0, 3 mu + H > 0");
-  // plane stress (2D linear elasticity): sig_33 = 0 eliminates eps_33, which leaves the 2D law with
-  // the reduced first Lame parameter 2 lam mu / (lam + 2 mu)
+  // plane stress, linear elasticity and St. Venant-Kirchhoff: both energies are quadratic in the
+  // strain (eps, resp. E = (F^T F - I)/2) with the same Lame form, so the out-of-plane normal stress
+  // = 0 eliminates the out-of-plane strain and leaves the 2D law with the reduced first Lame
+  // parameter 2 lam mu / (lam + 2 mu).  Neo-Hookean runs its own law, which solves for F33 per
+  // voxel: its Newton iteration needs lam >= 0 and mu > 0.
   std::vector<double> reduced;
-  if (h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) {
+  if ((h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) && h->desc.material == FFT_HOMOG_NEO_HOOKEAN) {
+    for (size_t k = 0; k < (size_t)2 * h->desc.nphase * cells; k += 2)
+      if (!(lm[k] >= 0.0) || !(lm[k + 1] > 0.0))
+        return fail(h, FFT_HOMOG_EINVAL, "Neo-Hookean plane stress needs lam >= 0 and mu > 0");
+  } else if (h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) {
     reduced.assign(lm, lm + (size_t)2 * h->desc.nphase * cells);
     for (size_t k = 0; k < reduced.size(); k += 2) {
       const double la = reduced[k], m = reduced[k + 1];
@@ -1567,7 +1582,7 @@ int fft_homog_project_noalloc(const fft_homog_desc* d, const double* in, double*
   const hipStream_t s = (hipStream_t)hip_stream;
   for (int a = 0; a < d->ndim && e == hipSuccess; ++a) e = launch_plan_tables(&pl[a], (double2*)(base + tw_off[a]), s, true);
   if (d->ndim == 2) pl[2] = pl[1];
-  const int matcode = 2 * d->material + (d->ndim - 2);
+  const int matcode = material_code(d);
   if (e == hipSuccess) e = set_smem_limits(g, matcode, L.smem_max);
   if (e == hipSuccess) e = enqueue_projection(g, pl, L, matcode, in, out, (double2*)(base + spec_off), batch, s);
   if (e != hipSuccess) return create_fail(FFT_HOMOG_EDEVICE, "projection launch", e);

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kThreads) k_homogenize(const double* F, MatPar
 #pragma unroll
     for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
     load_local<MAT, NDIM>(m, v, L);
-    if (MAT == MAT_NH || MAT == MAT_STVK) {
+    if (finite_mat(MAT)) {
       const double J = det_packed<NDIM>(e);
       if (!(finite_bits(J) && J > 0.0)) st[0].domain = 1;
     }

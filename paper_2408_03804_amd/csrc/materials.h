@@ -27,7 +27,11 @@
 
 namespace fh {
 
-enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2, MAT_J2 = 3 };
+// MAT_NH_PS: Neo-Hookean under plane stress (2D only)
+enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2, MAT_J2 = 3, MAT_NH_PS = 4 };
+
+// finite strain: the packed strain is a deformation gradient, whose determinant must stay positive
+constexpr bool finite_mat(int mat) { return mat == MAT_NH || mat == MAT_STVK || mat == MAT_NH_PS; }
 
 // Parameters and state of one voxel: Lame parameters, and for J2 the yield stress,
 // hardening modulus and plastic history (packed plastic strain, cumulative plastic strain)
@@ -48,6 +52,7 @@ template <> struct MatTraits<MAT_NH, 2> { static constexpr int C = 4; };
 template <> struct MatTraits<MAT_NH, 3> { static constexpr int C = 9; };
 template <> struct MatTraits<MAT_STVK, 2> { static constexpr int C = 4; };
 template <> struct MatTraits<MAT_STVK, 3> { static constexpr int C = 9; };
+template <> struct MatTraits<MAT_NH_PS, 2> { static constexpr int C = 4; };
 
 template <int MAT, int NDIM, class S>
 struct Energy;
@@ -122,6 +127,40 @@ struct Energy<MAT_STVK, 2, S> {
     return (0.5 * lam) * (tr * tr) + mu * EE;
   }
 };
+
+// ---- finite strain, Neo-Hookean under plane stress (2D) ------------------------
+// The 2D gradient F2 is completed to F = [[F2, 0], [0, F33]] with F33 = e^t chosen so that P33 of
+// the 3D law vanishes (the out-of-plane shear stresses vanish by isotropy).  With J2 = det F2,
+//   g(t) = F33 P33 = mu e^{2t} + lam (ln J2 + t) - mu,
+// which for lam >= 0, mu > 0 is increasing and convex in t: Newton's method from t = 0 converges
+// from either side of the root (after the first step the iterates fall monotonically onto it).
+// Stress and energy are the 3D law's at that F.  The energy is stationary in F33, so P needs only
+// the value of t; its derivative along dF2 needs dt = -lam (dJ2 / J2) / g'(t), which one Newton
+// step taken in the dual type from the converged root gives exactly (g = 0 there).  Returns psi.
+template <class T>
+__device__ inline T nh_plane_stress(const T* F, double lam, double mu, T* P) {
+  const T J2 = F[0] * F[3] - F[1] * F[2];
+  const T lnJ2 = dlog(J2);
+  const double l2 = val(lnJ2);
+  double t = 0.0;
+  for (int it = 0; it < 64; ++it) {
+    const double e2 = exp(2.0 * t);
+    const double dt = (mu * e2 + lam * (l2 + t) - mu) / (2.0 * mu * e2 + lam);
+    t -= dt;
+    if (!(fabs(dt) > 1e-15 * (1.0 + fabs(t)))) break;  // converged (or not finite: no more steps)
+  }
+  const double e2 = exp(2.0 * t);
+  const T tt = t - ((lnJ2 + t) * lam + (mu * e2 - mu)) * (1.0 / (2.0 * mu * e2 + lam));
+  const T lnJ = lnJ2 + tt;
+  const T F33 = dexp(tt);
+  const T c = (lnJ * lam - mu) / J2;  // (lam ln J - mu) / J2: F2^-T = [[F3, -F2], [-F1, F0]] / J2
+  P[0] = mu * F[0] + c * F[3];
+  P[1] = mu * F[1] - c * F[2];
+  P[2] = mu * F[2] - c * F[1];
+  P[3] = mu * F[3] + c * F[0];
+  const T I1 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2] + F[3] * F[3] + F33 * F33;
+  return (0.5 * mu) * (I1 - 3.0) - mu * lnJ + (0.5 * lam) * (lnJ * lnJ);
+}
 
 // ---- J2 return mapping (generic in the scalar type) ---------------------------
 // Packed Mandel strain e (C components; 2D plane strain: [e11, e22, sqrt2 e12], e33 = 0).
@@ -218,6 +257,8 @@ __device__ inline double stress_ad(const double* e, const Local& L, double* P) {
     j2_return<NDIM, double>(e, L, sig6, dp, N6, pl);
     j2_pack<NDIM, double>(sig6, P);
     return j2_energy<NDIM>(e, L, sig6);
+  } else if constexpr (MAT == MAT_NH_PS) {
+    return nh_plane_stress<double>(e, L.lam, L.mu, P);
   } else {
     Dual<double, C> x[C];
 #pragma unroll
@@ -249,6 +290,16 @@ __device__ inline void tangent_jvp_ad(const double* e, const double* de, const L
     }
     j2_return<NDIM, T>(x, L, sig6, dp, N6, pl);
     j2_pack<NDIM, T>(sig6, o);
+#pragma unroll
+    for (int k = 0; k < C; ++k) out[k] = o[k].d[0];
+  } else if constexpr (MAT == MAT_NH_PS) {
+    T x[C], o[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      x[k].v = e[k];
+      x[k].d[0] = de[k];
+    }
+    nh_plane_stress<T>(x, L.lam, L.mu, o);
 #pragma unroll
     for (int k = 0; k < C; ++k) out[k] = o[k].d[0];
   } else {
@@ -294,6 +345,20 @@ __device__ inline double stress_and_jvp_ad(const double* e, const double* de, co
       KdE[k] = o[k].d[0];
     }
     return j2_energy<NDIM>(e, L, s6);
+  } else if constexpr (MAT == MAT_NH_PS) {
+    T x[C], o[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      x[k].v = e[k];
+      x[k].d[0] = de[k];
+    }
+    const T psi = nh_plane_stress<T>(x, L.lam, L.mu, o);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      P[k] = o[k].v;
+      KdE[k] = o[k].d[0];
+    }
+    return psi.v;
   } else {
     Dual<T, C> x[C];
 #pragma unroll

@@ -29,7 +29,7 @@
 
 namespace fh {
 
-// matcode = 2 * material + (ndim - 2)
+// matcode = 2 * material + (ndim - 2); 8: Neo-Hookean under plane stress (2D)
 #define FH_DISPATCH_MAT(matcode, MACRO) \
   switch (matcode) {                    \
     case 0: MACRO(MAT_LE, 2); break;    \
@@ -40,6 +40,7 @@ namespace fh {
     case 5: MACRO(MAT_STVK, 3); break;  \
     case 6: MACRO(MAT_J2, 2); break;    \
     case 7: MACRO(MAT_J2, 3); break;    \
+    case 8: MACRO(MAT_NH_PS, 2); break; \
     default: return hipErrorInvalidValue; \
   }
 
@@ -296,7 +297,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
         for (int j = 0; j < C; ++j) e[j] = need_e ? a.F[j * N + vox] : 0.0;
       }
       if (PROD == PROD_STRESS) {
-        if (MAT == MAT_NH || MAT == MAT_STVK) {
+        if (finite_mat(MAT)) {
           const double J = det_packed<NDIM>(e);
           if (!(finite_bits(J) && J > 0.0)) bad = 1;
         }

@@ -141,6 +141,83 @@ class PlasticProblem(newton_cg.Problem):
         self.pending = False
 
 
+class PlasticPlaneStressProblem(PlasticProblem):
+    """2D J2 cell under plane stress: at each voxel the out-of-plane strain eps_33 takes the value at
+    which sigma_33 of the 3D return mapping (from that voxel's history) vanishes; eps_13 = eps_23 = 0
+    and the out-of-plane shear stresses vanish with them.  sigma_33 is continuous and increasing in
+    eps_33 (its slope is the consistent tangent's 3333 entry), so bisection on a bracket grown about
+    the elastic-trial root finds it.  The tangent is the consistent tangent condensed on eps_33."""
+
+    def __init__(self, shape, lam, mu, sy, H, lengths=None):
+        super().__init__(shape, lam, mu, sy, H, lengths)
+        if self.d != 2:
+            raise ValueError("plane stress is a 2D setting")
+        self._last = None
+
+    def _s33(self, E, z):
+        E3 = embed(E).copy()
+        E3[..., 2, 2] = z
+        return return_map(E3, self.ep, self.p, self.lam, self.mu, self.sy, self.H)[0][..., 2, 2]
+
+    def full(self, E):
+        """The 3D strain of the plane-stress state at in-plane strain E."""
+        if self._last is not None and self._last[0].shape == E.shape and np.array_equal(self._last[0], E) \
+                and self._last[1] is self.ep:
+            return self._last[2]
+        # elastic trial root: lam (e11 + e22 + z) + 2 mu (z - ep33) = 0
+        z0 = (2.0 * self.mu * self.ep[..., 2, 2] - self.lam * (E[..., 0, 0] + E[..., 1, 1])) / (self.lam + 2.0 * self.mu)
+        w = np.abs(E).max(axis=(-2, -1)) + np.abs(z0) + 1e-12
+        lo, hi = z0 - w, z0 + w
+        for _ in range(200):
+            bad = self._s33(E, lo) > 0
+            if not bad.any():
+                break
+            lo = np.where(bad, lo - 2 * w, lo)
+            w = np.where(bad, 2 * w, w)
+        for _ in range(200):
+            bad = self._s33(E, hi) < 0
+            if not bad.any():
+                break
+            hi = np.where(bad, hi + 2 * w, hi)
+            w = np.where(bad, 2 * w, w)
+        for _ in range(2000):
+            mid = 0.5 * (lo + hi)
+            done = (mid <= lo) | (mid >= hi)
+            if done.all():
+                break
+            up = self._s33(E, mid) > 0
+            hi = np.where(up & ~done, mid, hi)
+            lo = np.where(~up & ~done, mid, lo)
+        E3 = embed(E).copy()
+        E3[..., 2, 2] = 0.5 * (lo + hi)
+        self._last = (E.copy(), self.ep, E3)
+        return E3
+
+    def stress(self, E):
+        return super().stress3(self.full(E))[..., :2, :2]
+
+    def stress3(self, E):
+        return super().stress3(self.full(E))
+
+    def energy_density(self, E):
+        return super().energy_density(self.full(E))
+
+    def tangent_apply(self, E, dE):
+        E3 = self.full(E)
+        q = tangent_apply(E3, embed(dE), self.ep, self.p, self.lam, self.mu, self.sy, self.H)
+        u = np.zeros(E3.shape)
+        u[..., 2, 2] = 1.0
+        k = tangent_apply(E3, u, self.ep, self.p, self.lam, self.mu, self.sy, self.H)
+        dz = -q[..., 2, 2] / k[..., 2, 2]
+        return (q + dz[..., None, None] * k)[..., :2, :2]
+
+    def plastic_strain_now(self, E):
+        return super().plastic_strain_now(self.full(E))
+
+    def commit(self, E):
+        super().commit(self.full(E))
+
+
 def homogenized_tangent(problem, state, tol_cg=1e-10, max_cg=100000, zero_rhs_rel=1e-13):
     """Implicit homogenized tangent of the current (uncommitted) step: the linear-elastic
     machinery of newton_cg with the consistent tangent in place of the elastic one."""

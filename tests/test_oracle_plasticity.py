@@ -161,3 +161,94 @@ def test_unloading_to_zero_macro_strain_converges_with_residual_stresses():
     assert np.linalg.norm(prob.G(sig)) < 1e-8 * np.linalg.norm(sig)  # in equilibrium
     # under strain control the mean plastic strain leaves a macro stress at zero macro strain
     assert np.all(np.isfinite(r2["macro_stress"])) and np.abs(r2["macro_stress"]).max() > 0
+
+
+def _ps_problem(shape, lam, mu, sy, H, rng=None):
+    pr = P.PlasticPlaneStressProblem(shape, lam, mu, sy, H)
+    if rng is not None:  # a committed plastic history: deviatoric eps_p, p >= |eps_p|
+        A = 2e-3 * rng.standard_normal(shape + (3, 3))
+        ep = 0.5 * (A + np.swapaxes(A, -1, -2))
+        ep[..., 0, 2] = ep[..., 2, 0] = ep[..., 1, 2] = ep[..., 2, 1] = 0.0
+        ep[..., 2, 2] = -(ep[..., 0, 0] + ep[..., 1, 1])
+        pr.ep = ep
+        pr.p = np.sqrt(2.0 / 3.0 * np.einsum("...ij,...ij->...", ep, ep)) + 1e-3
+    return pr
+
+
+@pytest.mark.parametrize("history", [False, True])
+def test_plane_stress_j2_has_no_out_of_plane_stress_and_stays_on_the_surface(history):
+    """Pins the J2 plane-stress oracle: the 3D stress at the completed strain has no out-of-plane
+    entries, and where the step is plastic its von Mises stress is sig_y + H (p + dp)."""
+    rng = np.random.default_rng(50)
+    shape = (5, 8)
+    lam, mu = scal(1.3, shape), scal(0.8, shape)
+    sy, H = scal(4e-3, shape), scal(0.1, shape)
+    pr = _ps_problem(shape, lam, mu, sy, H, rng if history else None)
+    E = random_sym(rng, shape, 2, 1e-2)
+    s3 = pr.stress3(E)
+    scale = np.abs(s3).max()
+    assert np.abs(s3[..., 2, :]).max() < 1e-13 * scale and np.abs(s3[..., :, 2]).max() < 1e-13 * scale
+    _, dp, _ = P.return_map(pr.full(E), pr.ep, pr.p, lam, mu, sy, H)
+    assert (dp > 0).mean() > 0.5
+    dev = s3 - np.einsum("...ii->...", s3)[..., None, None] / 3.0 * np.eye(3)
+    seq = np.sqrt(1.5 * np.einsum("...ij,...ij->...", dev, dev))
+    pl = dp > 0
+    assert np.abs(seq[pl] - (sy + H * (pr.p + dp))[pl]).max() < 1e-12 * scale
+
+
+def test_plane_stress_j2_equibiaxial_closed_form():
+    """Equibiaxial in-plane strain e from a virgin state: sigma_11 = sigma_22 = sig_y + H dp with
+    dp = (2 mu (3 lam + 2 mu) e / (lam + 2 mu) - sig_y) / (mu (3 lam + 2 mu) / (lam + 2 mu) + H) and
+    eps_33 = -(2 lam e + 2 mu dp) / (lam + 2 mu), worked out by hand from sigma_33 = 0 and the radial
+    return (N = diag(1/2, 1/2, -1) for this stress)."""
+    lam, mu, sy, H = 1.7, 0.9, 3e-3, 0.15
+    e = np.array([[5e-4, 4e-3], [1e-2, 5e-2]])
+    shape = e.shape
+    pr = P.PlasticPlaneStressProblem(shape, lam, mu, sy, H)
+    E = e[..., None, None] * np.eye(2)
+    k = lam + 2 * mu
+    dp = np.maximum(2 * mu * (3 * lam + 2 * mu) * e / k - sy, 0.0) / (mu * (3 * lam + 2 * mu) / k + H)
+    elastic = dp == 0
+    assert elastic[0, 0] and elastic.sum() == 1
+    sig = np.where(elastic, 2 * mu * (3 * lam + 2 * mu) * e / k, sy + H * dp)
+    s = pr.stress(E)
+    assert np.abs(s[..., 0, 0] - sig).max() < 1e-14 and np.abs(s[..., 1, 1] - sig).max() < 1e-14
+    assert np.abs(s[..., 0, 1]).max() < 1e-16
+    e33 = -(2 * lam * e + 2 * mu * dp) / k
+    assert np.abs(pr.full(E)[..., 2, 2] - e33).max() < 1e-15
+
+
+def test_plane_stress_j2_below_yield_is_linear_plane_stress():
+    rng = np.random.default_rng(51)
+    shape = (4, 5)
+    lam, mu = rng.uniform(0.5, 2.0, shape), rng.uniform(0.3, 1.5, shape)
+    pr = P.PlasticPlaneStressProblem(shape, lam, mu, scal(1e3, shape), scal(0.1, shape))
+    E = random_sym(rng, shape, 2, 1e-2)
+    ref = materials.LinearElasticPlaneStress.stress(E, lam, mu)
+    assert np.abs(pr.stress(E) - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("history", [False, True])
+def test_plane_stress_j2_condensed_tangent_is_the_stress_derivative_and_symmetric(history):
+    rng = np.random.default_rng(52)
+    shape = (5, 6)
+    lam, mu = scal(1.3, shape), scal(0.8, shape)
+    sy, H = scal(4e-3, shape), scal(0.1, shape)
+    pr = _ps_problem(shape, lam, mu, sy, H, rng if history else None)
+    E = random_sym(rng, shape, 2, 1e-2)
+    dE = random_sym(rng, shape, 2, 1.0)
+    dG = random_sym(rng, shape, 2, 1.0)
+    h = 1e-8
+    fd = (pr.stress(E + h * dE) - pr.stress(E - h * dE)) / (2 * h)
+    K = pr.tangent_apply(E, dE)
+    assert np.abs(K - fd).max() < 1e-6 * np.abs(K).max()
+    KG = pr.tangent_apply(E, dG)
+    a = np.einsum("...ij,...ij->...", dG, K)
+    b = np.einsum("...ij,...ij->...", dE, KG)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    # plane stress is softer than plane strain along the in-plane normal strain
+    one = np.zeros(shape + (2, 2))
+    one[..., 0, 0] = 1.0
+    ps = pr.tangent_apply(E, one)[..., 0, 0]
+    pe = P.tangent_apply(pr.full(E), P.embed(one), pr.ep, pr.p, lam, mu, sy, H)[..., 0, 0]
+    assert (ps < pe).all()

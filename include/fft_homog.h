@@ -36,7 +36,7 @@
  *   determinism every reduction (CG dot products, Newton norms, homogenized averages) sums in a
  *               fixed order (wavefront shuffles, then fixed wave and block order; no atomics), so
  *               a repeated call on the same inputs and launch shape is bitwise identical.
- *   2D          plane strain unless FFT_HOMOG_FLAG_PLANE_STRESS (not for J2 plasticity).
+ *   2D          plane strain unless FFT_HOMOG_FLAG_PLANE_STRESS.
  */
 #ifndef FFT_HOMOG_H
 #define FFT_HOMOG_H
@@ -92,9 +92,10 @@ enum { FFT_HOMOG_K_RECOMPUTE = 0, FFT_HOMOG_K_STORED = 1 };
                                           normal stress of the 3D law vanishes at every voxel.
                                           Linear elasticity and St. Venant-Kirchhoff become their 2D
                                           laws with the reduced first Lame parameter
-                                          2 lam mu / (lam + 2 mu); Neo-Hookean solves for F33 per
-                                          voxel (set_material then needs lam >= 0, mu > 0) with the
-                                          tangent condensed on dF33.  EINVAL for 3D or J2 */
+                                          2 lam mu / (lam + 2 mu); Neo-Hookean solves for F33 and
+                                          J2 for eps_33 per voxel (set_material then needs lam >= 0,
+                                          mu > 0, resp. mu > 0, 3 lam + 2 mu > 0), with the tangent
+                                          condensed on the out-of-plane entry.  EINVAL for 3D */
 #define FFT_HOMOG_FLAG_GRAPH 4u    /* enqueue full chunks of CG iterations by replaying a captured
                                       HIP graph (built on first use, rebuilt after set_material or
                                       autotune); results are bitwise those of direct launches */

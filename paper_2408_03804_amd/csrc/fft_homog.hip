@@ -87,11 +87,12 @@ bool make_geom(const fft_homog_desc* d, Geom* g) {
   return true;
 }
 
-// kernel material code: 2 * material + (ndim - 2); Neo-Hookean under plane stress has a law of its
-// own (8), linear elasticity and St. Venant-Kirchhoff under plane stress are their 2D laws with a
-// reduced first Lame parameter (set_material converts the table)
+// kernel material code: 2 * material + (ndim - 2); Neo-Hookean and J2 under plane stress have laws
+// of their own (8, 9), linear elasticity and St. Venant-Kirchhoff under plane stress are their 2D
+// laws with a reduced first Lame parameter (set_material converts the table)
 static int material_code(const fft_homog_desc* d) {
   if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && d->material == FFT_HOMOG_NEO_HOOKEAN) return 8;
+  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && d->material == FFT_HOMOG_J2_PLASTIC) return 9;
   return 2 * d->material + (d->ndim - 2);
 }
 
@@ -119,8 +120,7 @@ int validate_desc(const fft_homog_desc* d) {
   if (d->batch < 0) return FFT_HOMOG_EINVAL;
   if (d->flags & ~(FFT_HOMOG_FLAG_TANGENT | FFT_HOMOG_FLAG_DENSITY | FFT_HOMOG_FLAG_GRAPH | FFT_HOMOG_FLAG_PLANE_STRESS))
     return FFT_HOMOG_EINVAL;
-  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && (d->ndim != 2 || d->material == FFT_HOMOG_J2_PLASTIC))
-    return FFT_HOMOG_EINVAL;
+  if ((d->flags & FFT_HOMOG_FLAG_PLANE_STRESS) && d->ndim != 2) return FFT_HOMOG_EINVAL;
   if (d->batch > 1) {
     // a multi-cell handle runs the tangent solves of every cell at the reference state
     if (!(d->flags & FFT_HOMOG_FLAG_TANGENT)) return FFT_HOMOG_EINVAL;
@@ -908,14 +908,20 @@ int fft_homog_set_material(fft_homog_t* h, const uint8_t* phase, const double* l
   // plane stress, linear elasticity and St. Venant-Kirchhoff: both energies are quadratic in the
   // strain (eps, resp. E = (F^T F - I)/2) with the same Lame form, so the out-of-plane normal stress
   // = 0 eliminates the out-of-plane strain and leaves the 2D law with the reduced first Lame
-  // parameter 2 lam mu / (lam + 2 mu).  Neo-Hookean runs its own law, which solves for F33 per
-  // voxel: its Newton iteration needs lam >= 0 and mu > 0.
+  // parameter 2 lam mu / (lam + 2 mu).  Neo-Hookean and J2 run laws of their own, which solve for
+  // the out-of-plane entry per voxel: Neo-Hookean's Newton iteration needs lam >= 0 and mu > 0, J2's
+  // (on a bracket) an increasing sigma_33, mu > 0 and 3 lam + 2 mu > 0.
   std::vector<double> reduced;
-  if ((h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) && h->desc.material == FFT_HOMOG_NEO_HOOKEAN) {
+  const bool ps = (h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) != 0;
+  if (ps && h->desc.material == FFT_HOMOG_NEO_HOOKEAN) {
     for (size_t k = 0; k < (size_t)2 * h->desc.nphase * cells; k += 2)
       if (!(lm[k] >= 0.0) || !(lm[k + 1] > 0.0))
         return fail(h, FFT_HOMOG_EINVAL, "Neo-Hookean plane stress needs lam >= 0 and mu > 0");
-  } else if (h->desc.flags & FFT_HOMOG_FLAG_PLANE_STRESS) {
+  } else if (ps && h->desc.material == FFT_HOMOG_J2_PLASTIC) {
+    for (size_t k = 0; k < (size_t)4 * h->desc.nphase * cells; k += 4)
+      if (!(lm[k + 1] > 0.0) || !(3.0 * lm[k] + 2.0 * lm[k + 1] > 0.0))
+        return fail(h, FFT_HOMOG_EINVAL, "J2 plane stress needs mu > 0 and 3 lam + 2 mu > 0");
+  } else if (ps) {
     reduced.assign(lm, lm + (size_t)2 * h->desc.nphase * cells);
     for (size_t k = 0; k < reduced.size(); k += 2) {
       const double la = reduced[k], m = reduced[k + 1];

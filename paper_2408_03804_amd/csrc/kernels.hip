@@ -237,10 +237,17 @@ __global__ void k_pack(const double* full, double* packed, Geom g) {
   }
 }
 
+// J2 (MAT_J2, or MAT_J2_PS under plane stress): history of the converged state at F of the step
+template <int MAT, int NDIM>
+__device__ inline void j2_commit_any(const double* e, const Local& L, double* h) {
+  if constexpr (MAT == MAT_J2_PS) j2_ps_commit(e, L, h);
+  else j2_commit<NDIM>(e, L, h);
+}
+
 // J2: move the plastic history to the converged state at F (one load step ends)
-template <int NDIM>
+template <int MAT, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_j2_commit(const double* F, MatParams m, double* hist, Geom g) {
-  constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  constexpr int C = MatTraits<MAT, NDIM>::C;
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
@@ -248,16 +255,16 @@ __global__ void __launch_bounds__(kThreads) k_j2_commit(const double* F, MatPara
   Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-  load_local<MAT_J2, NDIM>(m, v, L);
-  j2_commit<NDIM>(e, L, h);
+  load_local<MAT, NDIM>(m, v, L);
+  j2_commit_any<MAT, NDIM>(e, L, h);
 #pragma unroll
   for (int k = 0; k <= C; ++k) hist[k * N + v] = h[k];
 }
 
 // J2: cumulative plastic strain of the state at F (history plus this step's increment)
-template <int NDIM>
+template <int MAT, int NDIM>
 __global__ void __launch_bounds__(kThreads) k_j2_plastic(const double* F, MatParams m, double* out, Geom g) {
-  constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  constexpr int C = MatTraits<MAT, NDIM>::C;
   const long long N = g.N;
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (v >= N) return;
@@ -265,8 +272,8 @@ __global__ void __launch_bounds__(kThreads) k_j2_plastic(const double* F, MatPar
   Local L;
 #pragma unroll
   for (int j = 0; j < C; ++j) e[j] = F[j * N + v];
-  load_local<MAT_J2, NDIM>(m, v, L);
-  j2_commit<NDIM>(e, L, h);
+  load_local<MAT, NDIM>(m, v, L);
+  j2_commit_any<MAT, NDIM>(e, L, h);
   out[v] = h[C];
 }
 
@@ -567,15 +574,17 @@ hipError_t launch_pack(const double* full, double* packed, const Geom& g, hipStr
 }
 
 hipError_t launch_j2_commit(int mat, const double* F, MatParams m, double* hist, const Geom& g, hipStream_t s) {
-  if (mat == 6) hipLaunchKernelGGL((k_j2_commit<2>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
-  else if (mat == 7) hipLaunchKernelGGL((k_j2_commit<3>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
+  if (mat == 6) hipLaunchKernelGGL((k_j2_commit<MAT_J2, 2>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
+  else if (mat == 7) hipLaunchKernelGGL((k_j2_commit<MAT_J2, 3>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
+  else if (mat == 9) hipLaunchKernelGGL((k_j2_commit<MAT_J2_PS, 2>), vox_grid(g), dim3(kThreads), 0, s, F, m, hist, g);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_j2_plastic(int mat, const double* F, MatParams m, double* out, const Geom& g, hipStream_t s) {
-  if (mat == 6) hipLaunchKernelGGL((k_j2_plastic<2>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
-  else if (mat == 7) hipLaunchKernelGGL((k_j2_plastic<3>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
+  if (mat == 6) hipLaunchKernelGGL((k_j2_plastic<MAT_J2, 2>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
+  else if (mat == 7) hipLaunchKernelGGL((k_j2_plastic<MAT_J2, 3>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
+  else if (mat == 9) hipLaunchKernelGGL((k_j2_plastic<MAT_J2_PS, 2>), vox_grid(g), dim3(kThreads), 0, s, F, m, out, g);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

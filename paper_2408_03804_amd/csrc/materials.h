@@ -27,8 +27,11 @@
 
 namespace fh {
 
-// MAT_NH_PS: Neo-Hookean under plane stress (2D only)
-enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2, MAT_J2 = 3, MAT_NH_PS = 4 };
+// MAT_NH_PS, MAT_J2_PS: Neo-Hookean and J2 plasticity under plane stress (2D only)
+enum { MAT_LE = 0, MAT_NH = 1, MAT_STVK = 2, MAT_J2 = 3, MAT_NH_PS = 4, MAT_J2_PS = 5 };
+
+// J2 plasticity: per-voxel yield parameters and plastic history
+constexpr bool j2_mat(int mat) { return mat == MAT_J2 || mat == MAT_J2_PS; }
 
 // finite strain: the packed strain is a deformation gradient, whose determinant must stay positive
 constexpr bool finite_mat(int mat) { return mat == MAT_NH || mat == MAT_STVK || mat == MAT_NH_PS; }
@@ -53,6 +56,7 @@ template <> struct MatTraits<MAT_NH, 3> { static constexpr int C = 9; };
 template <> struct MatTraits<MAT_STVK, 2> { static constexpr int C = 4; };
 template <> struct MatTraits<MAT_STVK, 3> { static constexpr int C = 9; };
 template <> struct MatTraits<MAT_NH_PS, 2> { static constexpr int C = 4; };
+template <> struct MatTraits<MAT_J2_PS, 2> { static constexpr int C = 3; };
 
 template <int MAT, int NDIM, class S>
 struct Energy;
@@ -244,6 +248,137 @@ __device__ inline double j2_energy(const double* e, const Local& L, const double
   return w + 0.25 * dd / L.mu;
 }
 
+// ---- J2 under plane stress (2D) -------------------------------------------------
+// The packed 2D strain [e11, e22, sqrt2 e12] is completed to the 3D Mandel strain
+// [e11, e22, z, 0, 0, sqrt2 e12] and the history to [ep11, ep22, -(ep11 + ep22), 0, 0, sqrt2 ep12; p]
+// (the plastic strain stays deviatoric, with no out-of-plane shear), and the 3D return mapping
+// runs on them.  z = eps_33 makes sigma_33 vanish.  sigma_33(z) is continuous and increasing (its
+// slope, the 3333 entry of the consistent tangent, is positive for mu > 0, H >= 0,
+// 3 lam + 2 mu > 0): Newton's method from the elastic-trial root, kept inside a bracket that each
+// step narrows and bisecting when a step leaves it (the slope jumps where the elastic and plastic
+// branches meet), converges.  K : de is condensed on eps_33 from a second dual direction along z.
+__device__ inline void j2_ps_local(const Local& L, Local& L3) {
+  L3 = L;
+  L3.hist[2] = -(L.hist[0] + L.hist[1]);
+  L3.hist[3] = 0.0;
+  L3.hist[4] = 0.0;
+  L3.hist[5] = L.hist[2];
+  L3.hist[6] = L.hist[3];
+}
+
+template <class T>
+__device__ inline void j2_ps_strain(const T* e, const T& z, T* e3) {
+  e3[0] = e[0];
+  e3[1] = e[1];
+  e3[2] = z;
+  e3[3] = lift<T>(0.0);
+  e3[4] = lift<T>(0.0);
+  e3[5] = e[2];
+}
+
+__device__ inline double j2_ps_e33(const double* e, const Local& L3) {
+  typedef Dual<double, 1> T;
+  // trial sigma_33 = lam (e11 + e22 + z) + 2 mu (z - ep33) vanishes here
+  double z = (2.0 * L3.mu * L3.hist[2] - L3.lam * (e[0] + e[1])) / (L3.lam + 2.0 * L3.mu);
+  const double scale = fabs(e[0]) + fabs(e[1]) + fabs(e[2]) + fabs(z);
+  double lo = -1e300, hi = 1e300;
+  for (int it = 0; it < 100; ++it) {
+    T x[3], zz, e3[6], sig6[6], N6[6], dp;
+    bool pl;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      x[k].v = e[k];
+      x[k].d[0] = 0.0;
+    }
+    zz.v = z;
+    zz.d[0] = 1.0;
+    j2_ps_strain<T>(x, zz, e3);
+    j2_return<3, T>(e3, L3, sig6, dp, N6, pl);
+    const double f = sig6[2].v, df = sig6[2].d[0];
+    const double step = f / df;
+    // converged: take the last step, which may be below half an ulp of z (also stops on a
+    // non-finite step; the stress then carries it to the domain checks)
+    if (!(fabs(step) > 1e-15 * scale)) {
+      if (f != 0.0) z -= step;
+      break;
+    }
+    if (f < 0.0) lo = z;
+    else hi = z;
+    double zn = z - step;
+    // bisect only inside a finite bracket: with a positive slope a step above the tolerance moves
+    // away from the bracket side it came from, so it can leave the bracket only past a finite side
+    if (!(zn > lo && zn < hi) && lo > -1e300 && hi < 1e300) zn = 0.5 * (lo + hi);
+    z = zn;
+  }
+  return z;
+}
+
+// stress (in-plane Mandel) and stored elastic energy
+__device__ inline double j2_ps_stress(const double* e, const Local& L, double* P) {
+  Local L3;
+  j2_ps_local(L, L3);
+  const double z = j2_ps_e33(e, L3);
+  double e3[6], sig6[6], N6[6], dp;
+  bool pl;
+  j2_ps_strain<double>(e, z, e3);
+  j2_return<3, double>(e3, L3, sig6, dp, N6, pl);
+  P[0] = sig6[0];
+  P[1] = sig6[1];
+  P[2] = sig6[5];
+  return j2_energy<3>(e3, L3, sig6);
+}
+
+// stress, K : de (condensed on eps_33) and stored elastic energy
+__device__ inline double j2_ps_stress_jvp(const double* e, const double* de, const Local& L, double* P,
+                                          double* KdE) {
+  typedef Dual<double, 2> T;
+  Local L3;
+  j2_ps_local(L, L3);
+  const double z = j2_ps_e33(e, L3);
+  T x[3], zz, e3[6], sig6[6], N6[6], dp;
+  bool pl;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    x[k].v = e[k];
+    x[k].d[0] = de[k];
+    x[k].d[1] = 0.0;
+  }
+  zz.v = z;
+  zz.d[0] = 0.0;
+  zz.d[1] = 1.0;
+  j2_ps_strain<T>(x, zz, e3);
+  j2_return<3, T>(e3, L3, sig6, dp, N6, pl);
+  const double dz = -sig6[2].d[0] / sig6[2].d[1];
+  const int idx[3] = {0, 1, 5};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P[k] = sig6[idx[k]].v;
+    KdE[k] = sig6[idx[k]].d[0] + sig6[idx[k]].d[1] * dz;
+  }
+  double ev[6], s6[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    ev[k] = e3[k].v;
+    s6[k] = sig6[k].v;
+  }
+  return j2_energy<3>(ev, L3, s6);
+}
+
+// history of the converged plane-stress state
+__device__ inline void j2_ps_commit(const double* e, const Local& L, double* hist_out) {
+  Local L3;
+  j2_ps_local(L, L3);
+  const double z = j2_ps_e33(e, L3);
+  double e3[6], sig6[6], N6[6], dp;
+  bool pl;
+  j2_ps_strain<double>(e, z, e3);
+  j2_return<3, double>(e3, L3, sig6, dp, N6, pl);
+  hist_out[0] = L.hist[0] + dp * N6[0];
+  hist_out[1] = L.hist[1] + dp * N6[1];
+  hist_out[2] = L.hist[2] + dp * N6[5];
+  hist_out[3] = L.hist[3] + dp;
+}
+
 // ---- derivatives by forward-mode AD -------------------------------------------
 
 // psi and its gradient (the stress) at e: one vector-dual pass.  J2: the return-mapped
@@ -259,6 +394,8 @@ __device__ inline double stress_ad(const double* e, const Local& L, double* P) {
     return j2_energy<NDIM>(e, L, sig6);
   } else if constexpr (MAT == MAT_NH_PS) {
     return nh_plane_stress<double>(e, L.lam, L.mu, P);
+  } else if constexpr (MAT == MAT_J2_PS) {
+    return j2_ps_stress(e, L, P);
   } else {
     Dual<double, C> x[C];
 #pragma unroll
@@ -302,6 +439,9 @@ __device__ inline void tangent_jvp_ad(const double* e, const double* de, const L
     nh_plane_stress<T>(x, L.lam, L.mu, o);
 #pragma unroll
     for (int k = 0; k < C; ++k) out[k] = o[k].d[0];
+  } else if constexpr (MAT == MAT_J2_PS) {
+    double P[C];
+    j2_ps_stress_jvp(e, de, L, P, out);
   } else {
     Dual<T, C> x[C];
 #pragma unroll
@@ -359,6 +499,8 @@ __device__ inline double stress_and_jvp_ad(const double* e, const double* de, co
       KdE[k] = o[k].d[0];
     }
     return psi.v;
+  } else if constexpr (MAT == MAT_J2_PS) {
+    return j2_ps_stress_jvp(e, de, L, P, KdE);
   } else {
     Dual<T, C> x[C];
 #pragma unroll

@@ -29,7 +29,7 @@
 
 namespace fh {
 
-// matcode = 2 * material + (ndim - 2); 8: Neo-Hookean under plane stress (2D)
+// matcode = 2 * material + (ndim - 2); 8, 9: Neo-Hookean, J2 under plane stress (2D)
 #define FH_DISPATCH_MAT(matcode, MACRO) \
   switch (matcode) {                    \
     case 0: MACRO(MAT_LE, 2); break;    \
@@ -41,6 +41,7 @@ namespace fh {
     case 6: MACRO(MAT_J2, 2); break;    \
     case 7: MACRO(MAT_J2, 3); break;    \
     case 8: MACRO(MAT_NH_PS, 2); break; \
+    case 9: MACRO(MAT_J2_PS, 2); break; \
     default: return hipErrorInvalidValue; \
   }
 
@@ -56,8 +57,8 @@ __device__ __forceinline__ void load_local(const MatParams& m, long long v, Loca
     L.lam *= s;
     L.mu *= s;
   }
-  if constexpr (MAT == MAT_J2) {
-    constexpr int C = MatTraits<MAT_J2, NDIM>::C;
+  if constexpr (j2_mat(MAT)) {
+    constexpr int C = MatTraits<MAT, NDIM>::C;
     L.sy = row[2];
     L.H = row[3];
 #pragma unroll
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(XFwdArgs a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) E[j * nv + t] = ld_stream(a.F + j * N + vox);
       }
-      if (MAT != MAT_J2) {
+      if (!j2_mat(MAT)) {
         Local L;
         load_local<MAT, NDIM>(mat, vox, L);  // brings the phase id and table line into cache
         (void)L;

@@ -2,9 +2,11 @@
 
 Neo-Hookean runs a law of its own (the out-of-plane stretch solved per voxel by Newton's method in
 the kernel, its derivative by one dual-number Newton step); St. Venant-Kirchhoff runs the 2D law
-with the reduced first Lame parameter.  The oracle completes F with the F33 at which the 3D law's
-P33 vanishes (bisection for Neo-Hookean, closed form for St. Venant-Kirchhoff) and condenses the 3D
-tangent on dF33.
+with the reduced first Lame parameter; J2 solves for eps_33 per voxel through the 3D return mapping
+(bracketed Newton) and condenses K on it with a second dual direction.  The oracle completes the
+strain with the out-of-plane entry at which the 3D law's out-of-plane normal stress vanishes
+(bisection for Neo-Hookean and J2, closed form for St. Venant-Kirchhoff) and condenses the 3D
+tangent on it.
 """
 
 import numpy as np
@@ -103,7 +105,80 @@ def test_plane_stress_argument_checks():
     with pytest.raises(FFTHomogError) as ei:
         h.set_material(phase, [[-0.5, 1.0], [2.0, 2.0]])
     assert ei.value.status == "einval"
-    with pytest.raises(FFTHomogError):
-        make(shape, "small", "j2_plastic", plane_stress=True)
+    g = make(shape, "small", "j2_plastic", plane_stress=True)
+    with pytest.raises(FFTHomogError) as ei:
+        g.set_material(phase, [[1.0, 0.0, 0.01, 0.1], [2.0, 1.0, 0.01, 0.1]])
+    assert ei.value.status == "einval"
     with pytest.raises(FFTHomogError):
         make((4, 5, 6), "finite", "neo_hookean", plane_stress=True)
+
+
+def j2_table(E=(1.0, 2.0), sy=(0.005, 0.01), H=(0.1, 0.2)):
+    return np.array([[*workloads.lame(E[i], 0.3), sy[i], H[i]] for i in range(2)])
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (16, 9)])
+def test_j2_plane_stress_return_mapping_matches_oracle(shape):
+    """J2 under plane stress from a virgin history: P, the condensed K : dE and the stored elastic
+    energy at every voxel against the oracle (eps_33 by bisection there, by bracketed Newton here)."""
+    from oracle import plasticity as OP
+    tab = j2_table()
+    phase = workloads.random_phases(shape, 2, 2)
+    h = make(shape, "small", "j2_plastic", plane_stress=True)
+    h.set_material(phase, tab)
+    rng = np.random.default_rng(6)
+    A = 0.02 * rng.standard_normal(shape + (2, 2))
+    E = 0.5 * (A + np.swapaxes(A, -1, -2))
+    B = rng.standard_normal(shape + (2, 2))
+    dE = 0.5 * (B + np.swapaxes(B, -1, -2))
+    P, K, psi = h.debug_constitutive(pack(E, True), pack(dE, True))
+    lam, mu, sy, H = [tab[phase, k] for k in range(4)]
+    pr = OP.PlasticPlaneStressProblem(shape, lam, mu, sy, H)
+    _, dp, _ = OP.return_map(pr.full(E), pr.ep, pr.p, lam, mu, sy, H)
+    assert (dp > 0).mean() > 0.5
+    assert field_err(P.cpu().numpy(), pack(pr.stress(E), True)) < 1e-13
+    assert field_err(K.cpu().numpy(), pack(pr.tangent_apply(E, dE), True)) < 1e-12
+    assert field_err(psi.cpu().numpy(), pr.energy_density(E)) < 1e-12
+
+
+def test_j2_plane_stress_disk_loading_unloading_path_matches_oracle():
+    """Hard disk in a soft matrix under plane stress: biaxial loading in 4 increments, unloading in 2,
+    then a sheared reload in 3; after each solve the fields, stress, cumulative plastic strain,
+    homogenized stress and energy, and the homogenized consistent tangent against the oracle."""
+    from oracle import plasticity as OP
+    n = 24
+    shape = (n, n)
+    phase = workloads.centered_disk(n, 0.25)
+    tab = j2_table()
+    h = make(shape, "small", "j2_plastic", tangent=True, tol_cg=1e-12, plane_stress=True)
+    h.set_material(phase, tab)
+    lam, mu, sy, H = [tab[phase, k] for k in range(4)]
+    prob = OP.PlasticPlaneStressProblem(shape, lam, mu, sy, H)
+    state = None
+    first = None
+    for macro, n_inc in [(np.array([1e-2, 1e-2, 0.0]), 4), (np.array([5e-3, 5e-3, 0.0]), 2),
+                         (np.array([1e-2, 1.5e-2, 4e-3]), 3)]:
+        S, psi, st = h.solve(macro, n_inc)
+        ref = newton_cg.solve(prob, macro, n_increments=n_inc, tol_cg=1e-12, state=state)
+        state = ref["state"]
+        assert st["status"] == "ok" and ref["stats"]["status"] == "ok"
+        assert abs(st["newton"] - ref["stats"]["newton"]) <= 1
+        first = S if first is None else first
+        Fg = np.moveaxis(h.get_field(0).cpu().numpy().reshape((2, 2) + shape), (0, 1), (-2, -1))
+        Pg = np.moveaxis(h.get_field(1).cpu().numpy().reshape((2, 2) + shape), (0, 1), (-2, -1))
+        assert field_err(Fg - state.macro, state.field - state.macro) < TOL_FIELD
+        assert field_err(Pg, prob.stress(state.field)) < TOL_FIELD
+        pl = h.get_field(3).cpu().numpy()
+        plref = prob.plastic_strain_now(state.field)
+        assert np.abs(pl - plref).max() < TOL_FIELD * np.abs(plref).max()
+        assert np.abs(S - ref["macro_stress"]).max() < TOL_HOMOG * np.abs(ref["macro_stress"]).max()
+        assert abs(psi - ref["energy"]) < TOL_HOMOG * abs(ref["energy"])
+        C, _ = h.tangent()
+        Cref, _ = OP.homogenized_tangent(prob, state, tol_cg=1e-12)
+        assert np.abs(C - Cref).max() < TOL_HOMOG * np.abs(Cref).max()
+    assert float(pl.max()) > 1e-3
+    # plane stress is softer than plane strain under the first (biaxial) load
+    g = make(shape, "small", "j2_plastic", tol_cg=1e-12)
+    g.set_material(phase, tab)
+    S2, _, _ = g.solve(np.array([1e-2, 1e-2, 0.0]), 4)
+    assert first[0] < S2[0]

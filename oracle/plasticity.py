@@ -22,7 +22,9 @@ tests/test_oracle_plasticity.py check both facts.
 
 Tensors are full 3x3 (plane strain in 2D: eps_33 = 0, the plastic strain keeps
 its out-of-plane component eps_p33 = -(eps_p11 + eps_p22)).  The elastic part is
-the isotropic linear elastic law of materials.LinearElastic.
+the isotropic linear elastic law of materials.LinearElastic.  Plane stress
+(PlasticPlaneStressProblem) chooses eps_33 per point so that sigma_33 vanishes;
+the paper names plane stress with its 2D examples without writing it out.
 """
 
 import numpy as np

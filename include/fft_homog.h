@@ -248,6 +248,24 @@ int fft_homog_set_launch_shape(fft_homog_t* h, const int shape[7]);
  * partial sums). */
 int fft_homog_autotune(fft_homog_t* h, int reps, int shape[7]);
 
+/* Choose where the CG work vectors sit in the workspace.  F and the work vectors x, r, p lie at
+ * multiples of the component size from one another; on large grids (one right-hand side of
+ * 64 MiB or more) the layout keeps 16 MiB behind the half spectrum, and a stagger s moves x, r, p
+ * and the spectrum by s, 2 s, 3 s and 4 s bytes.  How the x passes' streams spread over the HBM
+ * channels depends on that placement and on the physical pages behind the workspace, so the
+ * candidates {0, 256 B, 16 KiB, 256 KiB, 2 MiB, 4 MiB} are timed on this handle (reps launches of
+ * the forward and inverse x passes each, work vectors zeroed) and the fastest is kept if it beats
+ * the current one by 2 %.  Results do not depend on the placement (same kernels, same reduction
+ * order): only the time does.  *stagger (may be NULL) receives the chosen s.  On smaller grids
+ * the only candidate is 0.  Call it between solves, not during one (the work vectors are
+ * overwritten); captured graphs are dropped.  EINVAL for reps < 1. */
+int fft_homog_tune_placement(fft_homog_t* h, int reps, size_t* stagger);
+
+/* Apply a work-vector stagger chosen elsewhere (see fft_homog_tune_placement): a multiple of 256
+ * bytes with 4 * stagger within the layout's slack (16 MiB on large grids, else 0), else EINVAL.
+ * Between solves only; the work vectors' contents are not moved. */
+int fft_homog_set_placement(fft_homog_t* h, size_t stagger);
+
 void fft_homog_destroy(fft_homog_t* h);
 const char* fft_homog_strerror(int status);
 /* Message of the last failure on handle h; with h == NULL, of the last failed

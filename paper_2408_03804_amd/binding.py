@@ -83,7 +83,8 @@ EXPORTS = [
     "fft_homog_debug_project", "fft_homog_debug_apply_operator", "fft_homog_debug_cg",
     "fft_homog_debug_cg_chunk", "fft_homog_debug_time_cg",
     "fft_homog_set_kernel_timing", "fft_homog_get_kernel_timing",
-    "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune",
+    "fft_homog_get_launch_shape", "fft_homog_set_launch_shape", "fft_homog_autotune", "fft_homog_tune_placement",
+    "fft_homog_set_placement",
     "fft_homog_project_noalloc",
 ]
 
@@ -129,6 +130,8 @@ def load_library(path=LIB_PATH):
         "fft_homog_get_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_set_launch_shape": (I, [P, ctypes.POINTER(I)]),
         "fft_homog_autotune": (I, [P, I, ctypes.POINTER(I)]),
+        "fft_homog_tune_placement": (I, [P, I, ctypes.POINTER(S)]),
+        "fft_homog_set_placement": (I, [P, S]),
         "fft_homog_project_noalloc": (I, [ctypes.POINTER(Desc), P, P, I, P]),
     }
     for name, (res, args) in sig.items():
@@ -297,6 +300,15 @@ class FFTHomog:
         s = (ctypes.c_int * 7)()
         self._check(self.L.fft_homog_autotune(self.h, int(reps), s))
         return _shape_dict(s)
+
+    def tune_placement(self, reps=10):
+        """Time the work-vector placements and keep the fastest; returns the chosen stagger (bytes)."""
+        s = ctypes.c_size_t(0)
+        self._check(self.L.fft_homog_tune_placement(self.h, int(reps), ctypes.byref(s)))
+        return int(s.value)
+
+    def set_placement(self, stagger):
+        self._check(self.L.fft_homog_set_placement(self.h, int(stagger)))
 
     def reset(self):
         """Back to the undeformed reference state (eps = 0 / F = I) with zero macro load."""

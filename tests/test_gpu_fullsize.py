@@ -44,8 +44,9 @@ def nh128():
     shape = w["shape"]
     h = make(shape, "finite", "neo_hookean", tol_newton=1e-10, tol_cg=1e-10, max_newton=50, max_cg=20000)
     h.set_material(w["phase"], w["table"])
+    stagger = h.tune_placement(reps=10)  # as bench.py does before its timed solves
     S, psi, st = h.solve(w["macro"], w["n_increments"])
-    return dict(w=w, h=h, S=S, psi=psi, st=st)
+    return dict(w=w, h=h, S=S, psi=psi, st=st, stagger=stagger)
 
 
 def test_neohookean_128_bench_configuration(nh128):
@@ -159,3 +160,33 @@ def test_spheres_64_tangent_properties():
 def test_disk_31_grid_is_config_of_small_workload():
     w = workloads.workload_disk2d(31)
     assert int(w["phase"].sum()) == 185 and w["shape"] == (31, 31)
+
+
+def test_work_vector_placement_changes_no_result():
+    """The work vectors' placement (fft_homog_set_placement / tune_placement) moves pointers only:
+    a 100^3 Neo-Hookean solve is bitwise the same at every stagger candidate the tuner may pick."""
+    w = workloads.workload_neohookean3d(n=100)
+    shape = w["shape"]
+    out = []
+    for s in (0, 256, 4 << 20, None):
+        h = make(shape, "finite", "neo_hookean", tol_newton=1e-10, tol_cg=1e-10, max_newton=50, max_cg=20000)
+        h.set_material(w["phase"], w["table"])
+        if s is None:
+            s = h.tune_placement(reps=3)
+            assert s in (0, 256, 16 << 10, 256 << 10, 2 << 20, 4 << 20)
+        else:
+            h.set_placement(s)
+        S, psi, st = h.solve(w["macro"], 2)
+        assert st["status"] == "ok"
+        out.append((S, psi, st["cg"], h.get_field(0).cpu().numpy()))
+        del h
+    for S, psi, cg, F in out[1:]:
+        assert np.array_equal(S, out[0][0]) and psi == out[0][1] and cg == out[0][2]
+        assert np.array_equal(F, out[0][3])
+    # small grids keep no slack: only stagger 0 is valid
+    from paper_2408_03804_amd.binding import FFTHomogError
+    g = make((16, 16, 16), "finite", "neo_hookean")
+    g.set_material(np.zeros((16, 16, 16), dtype=np.uint8), [[2.0, 1.0], [4.0, 2.0]])
+    assert g.tune_placement(reps=1) == 0
+    with pytest.raises(FFTHomogError):
+        g.set_placement(256)

@@ -110,7 +110,27 @@ int main() {
     EXPECT(fft_homog_solve(nullptr, nullptr, 1, nullptr, nullptr, nullptr) == FFT_HOMOG_EINVAL);
     EXPECT(fft_homog_tangent(nullptr, nullptr, nullptr) == FFT_HOMOG_EINVAL);
     EXPECT(fft_homog_get_launch_shape(nullptr, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_tune_placement(nullptr, 1, nullptr) == FFT_HOMOG_EINVAL);
+    EXPECT(fft_homog_set_placement(nullptr, 0) == FFT_HOMOG_EINVAL);
     fft_homog_destroy(nullptr);
+    // plane stress: every law in 2D, none in 3D
+    for (int kin = 0; kin < 2; ++kin)
+      for (int m = 0; m < 2; ++m) {
+        fft_homog_desc ps = make(2, 31, 31, 1, kins[kin], mats[kin][m]);
+        ps.flags = FFT_HOMOG_FLAG_PLANE_STRESS;
+        EXPECT(fft_homog_workspace_size(&ps, &bytes) == FFT_HOMOG_OK);
+        fft_homog_desc ps3 = make(3, 8, 8, 8, kins[kin], mats[kin][m]);
+        ps3.flags = FFT_HOMOG_FLAG_PLANE_STRESS;
+        EXPECT(fft_homog_workspace_size(&ps3, &bytes) == FFT_HOMOG_EINVAL);
+      }
+    // large grids keep 16 MiB of placement slack behind the spectrum: the 128^3 finite-strain
+    // workspace exceeds its buffers' sum (F, x, r, p: 4 x 144 MiB; spectrum 9 x 65 x 128^2 x 16 B)
+    {
+      fft_homog_desc nh = make(3, 128, 128, 128, FFT_HOMOG_FINITE_STRAIN, FFT_HOMOG_NEO_HOOKEAN);
+      EXPECT(fft_homog_workspace_size(&nh, &bytes) == FFT_HOMOG_OK);
+      const size_t vecs = 4 * (size_t)9 * 128 * 128 * 128 * 8 + (size_t)9 * 72 * 128 * 128 * 16;
+      EXPECT(bytes >= vecs + (16u << 20));
+    }
   }
   // status strings
   for (int s = 0; s < 12; ++s) EXPECT(fft_homog_strerror(s) != nullptr);
